@@ -1,0 +1,189 @@
+"""Pins of the oracle's observations (Fig. 1: relative coordinate frame, 50 m radius;
+Sec. 3.2 "Sensor modalities": radius filter and LIDAR).
+
+Road top-K is compared with a library stable sort (numpy lexsort) of the binary32 key;
+ego-frame features with a complex-number rotation; invariance under rigid motions and
+permutations; LIDAR against closed-form wall and box distances.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from tests._util import key32, tiny_world, wrap
+
+
+@pytest.fixture(scope="module")
+def cfg1_two_worlds():
+    from paper_2408_01584_amd import scenes as S
+    return S.make_scene(1, worlds=[0, 5])
+
+
+def test_road_topk_matches_library_sort(oracle_mod, cfg1_two_worlds):
+    sc = cfg1_two_worlds
+    sim = oracle_mod.OracleSim(sc)
+    r = sim.reset()
+    K = sc.params.top_k
+    R2 = np.float32(np.float32(50.0) * np.float32(50.0))
+    for w in range(sc.num_worlds):
+        r0, r1 = sc.road_off[w], sc.road_off[w + 1]
+        for i in range(sc.agent_off[w], sc.agent_off[w + 1]):
+            k = key32(sc.x[i], sc.y[i], sc.road_x[r0:r1], sc.road_y[r0:r1])
+            cand = np.nonzero(k <= R2)[0]
+            order = cand[np.lexsort((cand, k[cand]))][:K]
+            got = r["road_idx"][i]
+            n = len(order)
+            assert np.array_equal(got[:n], order)
+            assert np.all(got[n:] == -1)
+            assert np.all(r["road"][i, n:] == 0.0)
+            # features: rotate by -yaw with complex arithmetic
+            q = (sc.road_x[r0:r1][order].astype(np.float64) + 1j * sc.road_y[r0:r1][order]) \
+                - (np.float64(sc.x[i]) + 1j * np.float64(sc.y[i]))
+            q = q * np.exp(-1j * np.float64(sc.yaw[i]))
+            np.testing.assert_allclose(r["road"][i, :n, 0], q.real, atol=1e-9)
+            np.testing.assert_allclose(r["road"][i, :n, 1], q.imag, atol=1e-9)
+            dd = wrap(r["road"][i, :n, 2] - (sc.road_dir[r0:r1][order] - np.float64(sc.yaw[i])))
+            np.testing.assert_allclose(dd, 0.0, atol=1e-9)
+            assert np.all(r["road"][i, :n, 2] >= -math.pi) and np.all(r["road"][i, :n, 2] < math.pi)
+            np.testing.assert_array_equal(r["road"][i, :n, 3], sc.road_meta[r0:r1][order] & 255)
+    # the workload really exercises the cut: most agents have more than K candidates
+    assert np.mean((r["road_idx"] >= 0).sum(1) == K) > 0.5
+
+
+def _rigid(sc, phi, tx, ty):
+    c, s = math.cos(phi), math.sin(phi)
+    out = sc.copy()
+    for xs, ys in (("x", "y"), ("goal_x", "goal_y"), ("road_x", "road_y")):
+        X, Y = getattr(sc, xs).astype(np.float64), getattr(sc, ys).astype(np.float64)
+        setattr(out, xs, (c * X - s * Y + tx))
+        setattr(out, ys, (s * X + c * Y + ty))
+    out.yaw = sc.yaw.astype(np.float64) + phi
+    out.road_dir = sc.road_dir.astype(np.float64) + phi
+    return out
+
+
+def test_rigid_motion_invariance(oracle_mod, cfg1_two_worlds):
+    """Ego-frame features do not change when the whole world is rotated and
+    translated; selected sets only change at near ties of the binary32 key."""
+    sc = cfg1_two_worlds
+    base = oracle_mod.OracleSim(sc).reset()
+    moved = oracle_mod.OracleSim(_rigid(sc, 0.83, 17.0, -9.0)).reset()
+    np.testing.assert_allclose(moved["ego"], base["ego"], atol=1e-9)
+    np.testing.assert_array_equal(moved["pmask"], base["pmask"])
+    np.testing.assert_allclose(moved["partner"][:, :2], base["partner"][:, :2], atol=1e-9)
+    np.testing.assert_allclose(wrap(moved["partner"][:, 2] - base["partner"][:, 2]), 0, atol=1e-9)
+    np.testing.assert_allclose(moved["partner"][:, 3:], base["partner"][:, 3:], atol=0)
+    checked = 0
+    for i in range(sc.num_agents):
+        a, b = base["road_idx"][i], moved["road_idx"][i]
+        fa, fb = base["road"][i], moved["road"][i]
+        # distances of the selected points, FP64, from the features
+        da = np.hypot(fa[:, 0], fa[:, 1])
+        n = (a >= 0).sum()
+        if n == 0:
+            continue
+        gaps = np.diff(np.sort(da[:n]))
+        near_tie = (gaps < 1e-3).any()
+        cut = base["band"][i] & 8
+        if set(a[a >= 0]) == set(b[b >= 0]):
+            oa, ob = np.argsort(a[:n]), np.argsort(b[:n])
+            np.testing.assert_allclose(fb[:n][ob, :2], fa[:n][oa, :2], atol=1e-9)
+            checked += 1
+        else:
+            assert cut or near_tie, i
+        if not near_tie:
+            assert np.array_equal(a, b), i
+    assert checked > 0.9 * sc.num_agents
+
+
+def test_road_permutation(oracle_mod):
+    """Permuting road points maps the selection through the permutation; the ranking
+    keys come out in the same ascending order."""
+    from paper_2408_01584_amd import scenes as S
+    sc = S.make_scene(0)
+    base = oracle_mod.OracleSim(sc).reset()
+    perm = np.random.default_rng(5).permutation(sc.num_road)
+    sp = sc.copy()
+    for k in ("road_x", "road_y", "road_dir", "road_meta"):
+        setattr(sp, k, getattr(sc, k)[perm])
+    got = oracle_mod.OracleSim(sp).reset()
+    for i in range(sc.num_agents):
+        a = base["road_idx"][i]
+        b = got["road_idx"][i]
+        assert (a >= 0).sum() == (b >= 0).sum()
+        n = (a >= 0).sum()
+        ka = key32(sc.x[i], sc.y[i], sc.road_x[a[:n]], sc.road_y[a[:n]])
+        kb = key32(sc.x[i], sc.y[i], sc.road_x[perm[b[:n]]], sc.road_y[perm[b[:n]]])
+        np.testing.assert_array_equal(ka, kb)
+        if n < sc.params.top_k or ka[-1] != key32(sc.x[i], sc.y[i], sc.road_x, sc.road_y)[
+                np.setdiff1d(np.arange(sc.num_road), a[:n])].min():
+            assert set(a[:n]) == set(perm[b[:n]])
+
+
+def test_radius_filter_inclusive_and_padding(oracle_mod):
+    """Distance <= R is observed (inclusive), beyond is not; unused slots are zero with
+    index -1; features are the relative position, angle and type."""
+    pts = [(49.99, 0.0, 0.3, 0), (50.0, 0.0, 0.0, 1), (0.0, -50.01, 0.0, 0), (3.0, 4.0, 1.0, 1)]
+    sc = tiny_world([(0.0, 0.0, 0.0, 4.5, 2.0)], extra_road=[(x, y, d, m | 256) for x, y, d, m in pts])
+    r = oracle_mod.OracleSim(sc).reset()
+    assert list(r["road_idx"][0]) == [3, 0, 1, -1, -1, -1, -1, -1]
+    np.testing.assert_allclose(r["road"][0, 0], [3.0, 4.0, 1.0, 1.0])
+    np.testing.assert_allclose(r["road"][0, 1], [49.99, 0.0, 0.3, 0.0], atol=1e-12)
+    np.testing.assert_allclose(r["road"][0, 2], [50.0, 0.0, 0.0, 1.0])
+    assert np.all(r["road"][0, 3:] == 0)
+
+
+def test_ties_break_by_index(oracle_mod):
+    pts = [(0.0, 10.0, 0.0, 0), (10.0, 0.0, 0.0, 0), (-10.0, 0.0, 0.0, 0), (0.0, -10.0, 0.0, 0),
+           (6.0, 8.0, 0.0, 0)]
+    sc = tiny_world([(0.0, 0.0, 0.3, 4.5, 2.0)], extra_road=[(x, y, d, m | 256) for x, y, d, m in pts],
+                    params=__import__("paper_2408_01584_amd.scenes", fromlist=["x"]).SimParams(
+                        top_k=3, partners=0))
+    r = oracle_mod.OracleSim(sc).reset()
+    assert list(r["road_idx"][0]) == [0, 1, 2]
+
+
+def test_partner_and_ego_features(oracle_mod):
+    """Two agents facing each other 10 m apart; goal 30 m ahead of agent 0."""
+    sc = tiny_world([(0.0, 0.0, 0.0, 4.5, 2.0), (10.0, 0.0, math.pi, 5.0, 2.5), (0.0, 60.0, 0.0, 4.5, 2.0)],
+                    goals=[(30.0, 0.0), (10.0, 40.0), (0.0, 0.0)], speeds=[3.0, 7.0, 1.0])
+    r = oracle_mod.OracleSim(sc).reset()
+    np.testing.assert_allclose(r["ego"][0], [3.0, 4.5, 2.0, 30.0, 0.0, 0.0, 0.0, 1.0], atol=1e-12)
+    # agent 1 faces -x (yaw is float32(pi)): its goal 40 m towards +y lies on its right,
+    # y' = -40 (the ego frame has +x ahead and +y to the left)
+    np.testing.assert_allclose(r["ego"][1, 3:5], [0.0, -40.0], atol=1e-5)
+    P = 2
+    # agent 0, slot 0 = agent 1: ahead 10 m, facing back (wrapped to -pi)
+    f = r["partner"][0 * P + 0]
+    np.testing.assert_allclose(f[[0, 1, 3, 4, 5]], [10.0, 0.0, 7.0, 5.0, 2.5], atol=1e-6)
+    assert abs(wrap(f[2] - math.pi)) < 1e-6
+    assert r["pmask"][0] == 1
+    # agent 0, slot 1 = agent 2 at 60 m: outside the radius
+    assert r["pmask"][1] == 0 and np.all(r["partner"][1] == 0)
+    # agent 1, slot 0 = agent 0: 10 m ahead of agent 1 as well
+    g = r["partner"][2]
+    np.testing.assert_allclose(g[[0, 1, 3, 4, 5]], [10.0, 0.0, 3.0, 4.5, 2.0], atol=1e-5)
+    assert abs(wrap(g[2] - math.pi)) < 1e-6 and -math.pi <= g[2] < math.pi
+
+
+def test_lidar_wall_and_box(oracle_mod):
+    """A wall x = 10 seen from the origin: ray at angle a hits at 10 / cos(a) when that
+    is within range; a box 20 m ahead (L = 4.5) is hit at 17.75 by the forward ray."""
+    from paper_2408_01584_amd import scenes as S
+    p = S.SimParams(top_k=4, partners=1, lidar_rays=30, lidar_range=50.0)
+    sc = tiny_world([(0.0, 0.0, 0.0, 4.5, 2.0)], edges=[[(10.0, -200.0), (10.0, 200.0)]], params=p)
+    r = oracle_mod.OracleSim(sc).reset()
+    ang = 2 * np.pi * np.arange(30) / 30
+    want = np.where(np.cos(ang) >= 10.0 / 50.0, 10.0 / np.maximum(np.cos(ang), 1e-9), 50.0)
+    np.testing.assert_allclose(r["lidar"][0], want, atol=1e-9)
+    np.testing.assert_array_equal(r["lidar_hit"][0], np.where(np.cos(ang) >= 0.2, 1, 0))
+    # rotate the agent: rays are evenly spaced from the heading
+    sc2 = tiny_world([(0.0, 0.0, 0.5, 4.5, 2.0), (20.0 * math.cos(0.5), 20.0 * math.sin(0.5), 0.5, 4.5, 2.0)],
+                     params=p)
+    r2 = oracle_mod.OracleSim(sc2).reset()
+    np.testing.assert_allclose(r2["lidar"][0, 0], 17.75, atol=1e-9)
+    assert r2["lidar_hit"][0, 0] == 2
+    # own box never occludes; the back ray sees nothing
+    assert r2["lidar"][0, 15] == 50.0 and r2["lidar_hit"][0, 15] == 0
+    # seen from the second agent, the first is 17.75 m behind
+    np.testing.assert_allclose(r2["lidar"][1, 15], 17.75, atol=1e-9)
