@@ -1,0 +1,462 @@
+// Host side of libgd.so: the C-ABI declared in include/gd.h.  Validates arguments,
+// lays out the caller's workspace, orders the observation work items (longest first),
+// and enqueues the kernels on the caller's stream.  No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gd_internal.h"
+
+namespace gdk {
+hipError_t launch_road_obs_impl(const SimArgs &a, const ObsItem *items, int n_items, int waves,
+                                int bins, int max_road, hipStream_t s);
+hipError_t launch_lidar_impl(const SimArgs &a, int max_agents, hipStream_t s);
+hipError_t launch_rollout_fwd_impl(const SimArgs &a, const float2 *actions, int T, int C,
+                                   float *rewards, float *ckpt, hipStream_t s);
+hipError_t launch_rollout_bwd_impl(const SimArgs &a, const float2 *actions, const float *ckpt,
+                                   int T, int C, const float *grad_rewards, float2 *grad_actions,
+                                   float *grad_state0, hipStream_t s);
+
+static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+Layout make_layout(int W, long long A, long long R, long long n_items) {
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L.grid = take(sizeof(WorldGrid) * (size_t)W);
+    L.cell_start = take(sizeof(int) * (size_t)W * kCellStride);
+    L.pt_xy = take(sizeof(float2) * (size_t)R);
+    L.pt_aux = take(sizeof(float2) * (size_t)R);
+    L.ecell_start = take(sizeof(int) * (size_t)W * kCellStride);
+    L.eseg = take(sizeof(float4) * (size_t)R);
+    L.eseg_id = take(sizeof(int) * (size_t)R);
+    L.snap = take(sizeof(float4) * (size_t)A);
+    L.pbase = take(sizeof(long long) * (size_t)W);
+    L.err = take(256);
+    L.items = take(sizeof(ObsItem) * (size_t)n_items);
+    L.total = off;
+    return L;
+}
+
+__global__ void k_snapshot(const float *x, const float *y, const float *yaw, const float *v,
+                           float4 *snap, int A) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < A) snap[i] = make_float4(x[i], y[i], yaw[i], v[i]);
+}
+
+}  // namespace gdk
+
+using namespace gdk;
+
+struct gd_sim {
+    gd_config cfg;
+    SimArgs args;
+    std::vector<int32_t> h_agent_off, h_road_off;
+    Layout lay;
+    ObsItem *d_items = nullptr;
+    int n_items = 0;
+    int waves = 8, bins = 256, chunk = 64;
+    int max_road = 0, max_agents = 0;
+    long long slots = 0;
+    // graph mode
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    hipGraphNode_t step_node = nullptr;
+    const void *graph_actions = nullptr;
+};
+
+static thread_local std::string g_err;
+
+static gd_status fail(gd_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+static gd_status hip_fail(hipError_t e, const char *what) {
+    return fail(GD_E_HIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+#define HIP_TRY(expr, what)                      \
+    do {                                         \
+        hipError_t e_ = (expr);                  \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+static gd_status check_config(const gd_config *c, const int32_t *h_agent_off,
+                              const int32_t *h_road_off) {
+    if (!c) return fail(GD_E_ARG, "cfg is NULL");
+    if (!h_agent_off || !h_road_off) return fail(GD_E_ARG, "host offsets are NULL");
+    if (c->num_worlds < 1) return fail(GD_E_ARG, "num_worlds must be >= 1 (got %d)", c->num_worlds);
+    if (c->top_k < 0 || c->top_k > GD_MAX_TOP_K)
+        return fail(GD_E_SIZE, "top_k must be in [0, %d] (got %d)", GD_MAX_TOP_K, c->top_k);
+    if (c->partners < -1) return fail(GD_E_ARG, "partners must be >= -1 (got %d)", c->partners);
+    if (c->episode_len < 1) return fail(GD_E_ARG, "episode_len must be >= 1");
+    if (c->lidar_rays < 0 || c->lidar_rays > GD_MAX_LIDAR_RAYS)
+        return fail(GD_E_SIZE, "lidar_rays must be in [0, %d]", GD_MAX_LIDAR_RAYS);
+    if (!(c->dt > 0.f) || !std::isfinite(c->dt)) return fail(GD_E_ARG, "dt must be > 0");
+    if (!(c->obs_radius > 0.f) || !std::isfinite(c->obs_radius)) return fail(GD_E_ARG, "obs_radius must be > 0");
+    if (!(c->goal_radius >= 0.f) || !std::isfinite(c->goal_radius)) return fail(GD_E_ARG, "goal_radius must be >= 0");
+    if (!(c->v_max > 0.f)) return fail(GD_E_ARG, "v_max must be > 0");
+    if (c->lidar_rays > 0 && !(c->lidar_range > 0.f)) return fail(GD_E_ARG, "lidar_range must be > 0");
+    if (!std::isfinite(c->collision_penalty)) return fail(GD_E_ARG, "collision_penalty must be finite");
+    if (!(c->cell_size >= 0.f) || !std::isfinite(c->cell_size)) return fail(GD_E_ARG, "cell_size must be >= 0");
+    if (!(c->obs_waves == 0 || c->obs_waves == 1 || c->obs_waves == 2 || c->obs_waves == 4 ||
+          c->obs_waves == 8 || c->obs_waves == 16))
+        return fail(GD_E_ARG, "obs_waves must be 0, 1, 2, 4, 8 or 16");
+    if (!(c->obs_bins == 0 || c->obs_bins == 64 || c->obs_bins == 128 || c->obs_bins == 256 ||
+          c->obs_bins == 512))
+        return fail(GD_E_ARG, "obs_bins must be 0, 64, 128, 256 or 512");
+    if (c->obs_chunk < 0) return fail(GD_E_ARG, "obs_chunk must be >= 0");
+    if (c->reserved[0] || c->reserved[1]) return fail(GD_E_ARG, "reserved fields must be zero");
+    const int W = c->num_worlds;
+    if (h_agent_off[0] != 0 || h_road_off[0] != 0) return fail(GD_E_ARG, "offsets must start at 0");
+    for (int w = 0; w < W; w++) {
+        long long na = (long long)h_agent_off[w + 1] - h_agent_off[w];
+        long long nr = (long long)h_road_off[w + 1] - h_road_off[w];
+        if (na < 0 || nr < 0) return fail(GD_E_ARG, "offsets must be non-decreasing (world %d)", w);
+        if (na > GD_MAX_AGENTS_PER_WORLD)
+            return fail(GD_E_SIZE, "world %d has %lld agents (max %d)", w, na, GD_MAX_AGENTS_PER_WORLD);
+        if (nr > GD_MAX_ROAD_PER_WORLD)
+            return fail(GD_E_SIZE, "world %d has %lld road points (max %d)", w, nr, GD_MAX_ROAD_PER_WORLD);
+    }
+    return GD_OK;
+}
+
+static long long partner_slots_of(const gd_config *c, const int32_t *h_agent_off) {
+    long long s = 0;
+    for (int w = 0; w < c->num_worlds; w++) {
+        long long n = h_agent_off[w + 1] - h_agent_off[w];
+        s += c->partners >= 0 ? n * c->partners : n * (n > 0 ? n - 1 : 0);
+    }
+    return s;
+}
+
+static void launch_shape(const gd_config *c, int &waves, int &bins, int &chunk) {
+    waves = c->obs_waves ? c->obs_waves : 8;
+    bins = c->obs_bins ? c->obs_bins : 256;
+    chunk = c->obs_chunk ? c->obs_chunk : 64;
+}
+
+// observation work items: chunks of one world's agents, costliest first (LPT order, so the
+// hardware dispatcher's in-order assignment acts as a longest-processing-time schedule)
+static std::vector<ObsItem> make_items(const gd_config *c, const int32_t *ao, const int32_t *ro,
+                                       int chunk) {
+    struct Rec {
+        ObsItem it;
+        double cost;
+    };
+    std::vector<Rec> v;
+    for (int w = 0; w < c->num_worlds; w++) {
+        int n = ao[w + 1] - ao[w];
+        double nr = ro[w + 1] - ro[w];
+        for (int s = 0; s < n; s += chunk) {
+            int e = std::min(n, s + chunk);
+            v.push_back({{w, ao[w] + s, ao[w] + e, 0}, (double)(e - s) * (nr + 256.0)});
+        }
+    }
+    std::stable_sort(v.begin(), v.end(), [](const Rec &x, const Rec &y) { return x.cost > y.cost; });
+    std::vector<ObsItem> out;
+    out.reserve(v.size());
+    for (auto &r : v) out.push_back(r.it);
+    return out;
+}
+
+static long long n_items_of(const gd_config *c, const int32_t *ao, int chunk) {
+    long long k = 0;
+    for (int w = 0; w < c->num_worlds; w++) {
+        int n = ao[w + 1] - ao[w];
+        k += (n + chunk - 1) / chunk;
+    }
+    return k;
+}
+
+extern "C" {
+
+const char *gd_last_error(void) { return g_err.c_str(); }
+
+gd_status gd_partner_slots(const gd_config *cfg, const int32_t *h_agent_off, int64_t *slots) {
+    if (!cfg || !h_agent_off || !slots) return fail(GD_E_ARG, "NULL argument");
+    if (cfg->num_worlds < 1) return fail(GD_E_ARG, "num_worlds must be >= 1");
+    *slots = partner_slots_of(cfg, h_agent_off);
+    return GD_OK;
+}
+
+gd_status gd_workspace_size(const gd_config *cfg, const int32_t *h_agent_off,
+                            const int32_t *h_road_off, size_t *bytes) {
+    gd_status st = check_config(cfg, h_agent_off, h_road_off);
+    if (st != GD_OK) return st;
+    if (!bytes) return fail(GD_E_ARG, "bytes is NULL");
+    int waves, bins, chunk;
+    launch_shape(cfg, waves, bins, chunk);
+    const int W = cfg->num_worlds;
+    Layout L = make_layout(W, h_agent_off[W], h_road_off[W], n_items_of(cfg, h_agent_off, chunk));
+    *bytes = L.total;
+    return GD_OK;
+}
+
+gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int32_t *h_road_off,
+                    const gd_buffers *b, void *stream, gd_sim **out) {
+    gd_status st = check_config(cfg, h_agent_off, h_road_off);
+    if (st != GD_OK) return st;
+    if (!b || !out) return fail(GD_E_ARG, "bufs/out is NULL");
+    *out = nullptr;
+    const int W = cfg->num_worlds;
+    const long long A = h_agent_off[W], R = h_road_off[W];
+    const void *need[] = {b->agent_off, b->road_off, b->x, b->y, b->yaw, b->speed, b->length,
+                          b->width, b->goal_x, b->goal_y, b->obs_ego, b->reward, b->flags,
+                          b->world_done, b->t, b->workspace};
+    const char *names[] = {"agent_off", "road_off", "x", "y", "yaw", "speed", "length", "width",
+                           "goal_x", "goal_y", "obs_ego", "reward", "flags", "world_done", "t",
+                           "workspace"};
+    for (size_t k = 0; k < sizeof(need) / sizeof(need[0]); k++)
+        if (!need[k]) return fail(GD_E_ARG, "buffer %s is NULL", names[k]);
+    if (R > 0 && (!b->road_x || !b->road_y || !b->road_dir || !b->road_meta))
+        return fail(GD_E_ARG, "road buffers are NULL");
+    const long long S = partner_slots_of(cfg, h_agent_off);
+    if (S > 0 && (!b->obs_partner || !b->partner_mask)) return fail(GD_E_ARG, "partner buffers are NULL");
+    if (cfg->top_k > 0 && A > 0 && (!b->obs_road || !b->road_idx)) return fail(GD_E_ARG, "road obs buffers are NULL");
+    if (cfg->lidar_rays > 0 && A > 0 && (!b->lidar || !b->lidar_hit)) return fail(GD_E_ARG, "lidar buffers are NULL");
+    if (((uintptr_t)b->workspace) & 255) return fail(GD_E_ARG, "workspace must be 256-byte aligned");
+    int waves, bins, chunk;
+    launch_shape(cfg, waves, bins, chunk);
+    std::vector<ObsItem> items = make_items(cfg, h_agent_off, h_road_off, chunk);
+    Layout L = make_layout(W, A, R, (long long)items.size());
+    if (b->workspace_bytes < L.total)
+        return fail(GD_E_SIZE, "workspace too small: %zu bytes, need %zu", b->workspace_bytes, L.total);
+    int max_road = 0, max_agents = 0;
+    for (int w = 0; w < W; w++) {
+        max_road = std::max(max_road, h_road_off[w + 1] - h_road_off[w]);
+        max_agents = std::max(max_agents, h_agent_off[w + 1] - h_agent_off[w]);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // device offsets must hold the host values
+    {
+        std::vector<int32_t> chk(W + 1);
+        HIP_TRY(hipMemcpyAsync(chk.data(), b->agent_off, sizeof(int32_t) * (W + 1), hipMemcpyDeviceToHost, s), "copy agent_off");
+        HIP_TRY(hipStreamSynchronize(s), "sync");
+        if (memcmp(chk.data(), h_agent_off, sizeof(int32_t) * (W + 1)))
+            return fail(GD_E_ARG, "device agent_off differs from h_agent_off");
+        HIP_TRY(hipMemcpyAsync(chk.data(), b->road_off, sizeof(int32_t) * (W + 1), hipMemcpyDeviceToHost, s), "copy road_off");
+        HIP_TRY(hipStreamSynchronize(s), "sync");
+        if (memcmp(chk.data(), h_road_off, sizeof(int32_t) * (W + 1)))
+            return fail(GD_E_ARG, "device road_off differs from h_road_off");
+    }
+    gd_sim *sim = new gd_sim();
+    sim->cfg = *cfg;
+    sim->h_agent_off.assign(h_agent_off, h_agent_off + W + 1);
+    sim->h_road_off.assign(h_road_off, h_road_off + W + 1);
+    sim->lay = L;
+    sim->waves = waves;
+    sim->bins = bins;
+    sim->chunk = chunk;
+    sim->max_road = max_road;
+    sim->max_agents = max_agents;
+    sim->slots = S;
+    sim->n_items = (int)items.size();
+    char *ws = (char *)b->workspace;
+    SimArgs &a = sim->args;
+    a.W = W;
+    a.A = (int)A;
+    a.R = (int)R;
+    a.K = cfg->top_k;
+    a.P = cfg->partners;
+    a.N = cfg->lidar_rays;
+    a.T_ep = cfg->episode_len;
+    a.flags = cfg->flags;
+    a.dt = cfg->dt;
+    a.R_obs = cfg->obs_radius;
+    {
+        volatile float r = cfg->obs_radius;
+        volatile float r2 = r * r;
+        a.R2_obs = r2;
+        volatile float gr = cfg->goal_radius;
+        volatile float g2 = gr * gr;
+        a.goal_r2 = g2;
+    }
+    a.vmax = cfg->v_max;
+    a.lidar_range = cfg->lidar_range;
+    a.penalty = cfg->collision_penalty;
+    a.agent_off = b->agent_off;
+    a.road_off = b->road_off;
+    a.x = b->x;
+    a.y = b->y;
+    a.yaw = b->yaw;
+    a.v = b->speed;
+    a.len = b->length;
+    a.wid = b->width;
+    a.gx = b->goal_x;
+    a.gy = b->goal_y;
+    a.rx = b->road_x;
+    a.ry = b->road_y;
+    a.rdir = b->road_dir;
+    a.rmeta = b->road_meta;
+    a.ego = b->obs_ego;
+    a.partner = b->obs_partner;
+    a.pmask = b->partner_mask;
+    a.road = b->obs_road;
+    a.road_idx = b->road_idx;
+    a.lidar = b->lidar;
+    a.lidar_hit = b->lidar_hit;
+    a.reward = b->reward;
+    a.fl = b->flags;
+    a.world_done = b->world_done;
+    a.t = b->t;
+    a.grid = (WorldGrid *)(ws + L.grid);
+    a.cell_start = (int *)(ws + L.cell_start);
+    a.pt_xy = (float2 *)(ws + L.pt_xy);
+    a.pt_aux = (float2 *)(ws + L.pt_aux);
+    a.ecell_start = (int *)(ws + L.ecell_start);
+    a.eseg = (float4 *)(ws + L.eseg);
+    a.eseg_id = (int *)(ws + L.eseg_id);
+    a.snap = (float4 *)(ws + L.snap);
+    a.pbase = (long long *)(ws + L.pbase);
+    a.err = (unsigned *)(ws + L.err);
+    sim->d_items = (ObsItem *)(ws + L.items);
+
+    std::vector<long long> pb(W);
+    long long acc = 0;
+    for (int w = 0; w < W; w++) {
+        pb[w] = acc;
+        long long n = h_agent_off[w + 1] - h_agent_off[w];
+        acc += cfg->partners >= 0 ? n * cfg->partners : n * (n > 0 ? n - 1 : 0);
+    }
+    hipError_t e;
+    if ((e = hipMemcpyAsync(a.pbase, pb.data(), sizeof(long long) * W, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(sim->d_items, items.data(), sizeof(ObsItem) * items.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemsetAsync(a.err, 0, 256, s)) != hipSuccess) {
+        delete sim;
+        return hip_fail(e, "workspace init");
+    }
+    if (A > 0) {
+        hipLaunchKernelGGL(k_snapshot, dim3((unsigned)((A + 255) / 256)), dim3(256), 0, s, a.x, a.y, a.yaw,
+                           a.v, a.snap, (int)A);
+        if ((e = hipGetLastError()) != hipSuccess) {
+            delete sim;
+            return hip_fail(e, "snapshot");
+        }
+    }
+    if ((e = launch_build_grid(a, cfg->cell_size, s)) != hipSuccess) {
+        delete sim;
+        return hip_fail(e, "grid build");
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) {
+        delete sim;
+        return hip_fail(e, "grid build sync");
+    }
+    *out = sim;
+    st = gd_reset(sim, nullptr, stream);
+    if (st != GD_OK) {
+        delete sim;
+        *out = nullptr;
+        return st;
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) {
+        delete sim;
+        *out = nullptr;
+        return hip_fail(e, "reset sync");
+    }
+    return GD_OK;
+}
+
+static gd_status enqueue_obs(gd_sim *sim, hipStream_t s) {
+    hipError_t e = launch_road_obs_impl(sim->args, sim->d_items, sim->n_items, sim->waves, sim->bins,
+                                        sim->max_road, s);
+    if (e != hipSuccess) return hip_fail(e, "road observation launch");
+    if (sim->args.N > 0) {
+        e = launch_lidar_impl(sim->args, sim->max_agents, s);
+        if (e != hipSuccess) return hip_fail(e, "lidar launch");
+    }
+    return GD_OK;
+}
+
+gd_status gd_reset(gd_sim *sim, const uint8_t *world_mask, void *stream) {
+    if (!sim) return fail(GD_E_ARG, "sim is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_world_step(sim->args, kModeReset, nullptr, world_mask, s);
+    if (e != hipSuccess) return hip_fail(e, "reset launch");
+    return enqueue_obs(sim, s);
+}
+
+gd_status gd_obs(gd_sim *sim, void *stream) {
+    if (!sim) return fail(GD_E_ARG, "sim is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_world_step(sim->args, kModeObs, nullptr, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "obs launch");
+    return enqueue_obs(sim, s);
+}
+
+gd_status gd_step(gd_sim *sim, const float *actions, void *stream) {
+    if (!sim) return fail(GD_E_ARG, "sim is NULL");
+    if (!actions && sim->args.A > 0) return fail(GD_E_ARG, "actions is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = launch_world_step(sim->args, kModeStep, (const float2 *)actions, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "step launch");
+    return enqueue_obs(sim, s);
+}
+
+gd_status gd_rollout_fwd(gd_sim *sim, const float *actions, int32_t T, int32_t ckpt_every,
+                         float *rewards, float *ckpt, void *stream) {
+    if (!sim) return fail(GD_E_ARG, "sim is NULL");
+    if (T < 0) return fail(GD_E_ARG, "T must be >= 0");
+    if (ckpt_every < 1 || ckpt_every > 32) return fail(GD_E_ARG, "ckpt_every must be in [1, 32]");
+    if (T == 0 || sim->args.A == 0) return GD_OK;
+    if (!actions || !rewards || !ckpt) return fail(GD_E_ARG, "NULL buffer");
+    hipError_t e = launch_rollout_fwd_impl(sim->args, (const float2 *)actions, T, ckpt_every, rewards,
+                                           ckpt, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rollout forward launch");
+    return GD_OK;
+}
+
+gd_status gd_rollout_bwd(gd_sim *sim, const float *actions, const float *ckpt, int32_t T,
+                         int32_t ckpt_every, const float *grad_rewards, float *grad_actions,
+                         float *grad_state0, void *stream) {
+    if (!sim) return fail(GD_E_ARG, "sim is NULL");
+    if (T < 0) return fail(GD_E_ARG, "T must be >= 0");
+    if (ckpt_every < 1 || ckpt_every > 32) return fail(GD_E_ARG, "ckpt_every must be in [1, 32]");
+    if (T == 0 || sim->args.A == 0) return GD_OK;
+    if (!actions || !ckpt || !grad_rewards || !grad_actions) return fail(GD_E_ARG, "NULL buffer");
+    hipError_t e = launch_rollout_bwd_impl(sim->args, (const float2 *)actions, ckpt, T, ckpt_every,
+                                           grad_rewards, (float2 *)grad_actions, grad_state0,
+                                           (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rollout backward launch");
+    return GD_OK;
+}
+
+gd_status gd_check(gd_sim *sim, void *stream) {
+    if (!sim) return fail(GD_E_ARG, "sim is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    unsigned word = 0;
+    HIP_TRY(hipMemcpyAsync(&word, sim->args.err, sizeof(unsigned), hipMemcpyDeviceToHost, s), "read error word");
+    HIP_TRY(hipStreamSynchronize(s), "sync");
+    if (word) {
+        HIP_TRY(hipMemsetAsync(sim->args.err, 0, sizeof(unsigned), s), "clear error word");
+        HIP_TRY(hipStreamSynchronize(s), "sync");
+        return fail(GD_E_NONFINITE, "non-finite action seen (error word 0x%x)", word);
+    }
+    return GD_OK;
+}
+
+gd_status gd_destroy(gd_sim *sim) {
+    if (!sim) return GD_OK;
+    if (sim->graph_exec) (void)hipGraphExecDestroy(sim->graph_exec);
+    if (sim->graph) (void)hipGraphDestroy(sim->graph);
+    delete sim;
+    return GD_OK;
+}
+
+}  // extern "C"

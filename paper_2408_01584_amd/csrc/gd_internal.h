@@ -1,0 +1,120 @@
+// Internal declarations of libgd.so: device-side argument blocks, workspace layout and
+// the launchers of each kernel file.  Not part of the public ABI (include/gd.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gd.h"
+
+namespace gdk {
+
+constexpr int kWave = 64;
+constexpr int kGridAxis = GD_GRID_MAX_CELLS_PER_AXIS;        // cells per axis, at most
+constexpr int kGridCells = kGridAxis * kGridAxis;            // cells per world, at most
+constexpr int kCellStride = kGridCells + 1;                  // CSR row length per world
+constexpr float kDefaultCell = 10.0f;
+
+// Per-world uniform grid over the road points (and, separately, over the road-edge
+// segments keyed by their first endpoint).  Built once by gd_create.
+struct WorldGrid {
+    float ox, oy;      // origin (minimum corner)
+    float cs, inv_cs;  // cell size and its reciprocal
+    int nx, ny;        // cells per axis (1..kGridAxis)
+    float max_seg;     // longest edge segment of the world (m)
+    int n_edge;        // number of edge segments
+};
+
+// Everything a kernel needs, passed by value.
+struct SimArgs {
+    int W, A, R;
+    int K, P, N, T_ep;
+    uint32_t flags;
+    float dt, R_obs, R2_obs, goal_r2, vmax, lidar_range, penalty;
+
+    // caller buffers
+    const int *agent_off, *road_off;
+    float *x, *y, *yaw, *v;
+    const float *len, *wid, *gx, *gy;
+    const float *rx, *ry, *rdir;
+    const int *rmeta;
+    float *ego, *partner;
+    uint8_t *pmask;
+    float *road;
+    int *road_idx;
+    float *lidar;
+    int *lidar_hit;
+    float *reward;
+    uint8_t *fl;
+    uint8_t *world_done;
+    int *t;
+
+    // workspace
+    WorldGrid *grid;
+    int *cell_start;   // [W * kCellStride]
+    float2 *pt_xy;     // [R] road points, cell-sorted per world
+    float2 *pt_aux;    // [R] (dir, bits: local index | type << 24), cell-sorted
+    int *ecell_start;  // [W * kCellStride]
+    float4 *eseg;      // [R] edge segments (x0, y0, x1, y1), cell-sorted
+    int *eseg_id;      // [R] world-local index k of the segment (k, k+1)
+    float4 *snap;      // [A] initial (x, y, yaw, speed)
+    long long *pbase;  // [W] first partner slot of each world
+    unsigned *err;     // device error word
+};
+
+// Work item of the observation kernel: agents [a0, a1) of world w.
+struct ObsItem {
+    int w, a0, a1, pad;
+};
+
+enum StepMode { kModeStep = 0, kModeObs = 1, kModeReset = 2 };
+
+// Workspace layout (byte offsets, each 256-aligned).
+struct Layout {
+    size_t grid, cell_start, pt_xy, pt_aux, ecell_start, eseg, eseg_id, snap, pbase, err,
+        items, total;
+};
+Layout make_layout(int W, long long A, long long R, long long n_items);
+
+// launchers (return hipError_t of the launch)
+hipError_t launch_build_grid(const SimArgs &a, float cell_size, hipStream_t s);
+hipError_t launch_world_step(const SimArgs &a, int mode, const float2 *actions,
+                             const uint8_t *mask, hipStream_t s);
+
+// LDS bytes the observation kernel needs for a given shape (0 = does not fit)
+size_t road_obs_lds_bytes(int waves, int bins, int K, int max_road);
+
+// ---------------------------------------------------------------- device helpers
+
+// binary32 squared distance with a fixed operation order (no contraction): the ranking
+// key and the radius / goal tests use exactly this.
+__device__ __forceinline__ float key32(float px, float py, float qx, float qy) {
+#pragma clang fp contract(off)
+    float dx = qx - px;
+    float dy = qy - py;
+    float a = dx * dx;
+    float b = dy * dy;
+    return a + b;
+}
+
+__device__ __forceinline__ float wrap_pi(float a) {
+    // to [-pi, pi)
+    const float two_pi = 6.283185307179586f;
+    const float inv = 0.15915494309189535f;
+    float k = floorf((a + 3.14159265358979323846f) * inv);
+    float r = a - k * two_pi;
+    if (r >= 3.14159265358979323846f) r -= two_pi;
+    if (r < -3.14159265358979323846f) r += two_pi;
+    return r;
+}
+
+// Cell of coordinate v on an axis of n cells (clamped; NaN maps to cell 0).  Monotone
+// non-decreasing in v, which is what makes range queries over cells exact.
+__device__ __forceinline__ int cell_coord(float v, float o, float inv_cs, int n) {
+    float f = floorf((v - o) * inv_cs);
+    if (!(f >= 0.0f)) return 0;
+    if (f >= (float)n) return n - 1;
+    return (int)f;
+}
+
+}  // namespace gdk

@@ -1,0 +1,148 @@
+"""ctypes binding of libgd.so with the same entry-point names as include/gd.h.
+
+Argument marshalling only: every step of the simulator runs in the HIP kernels of the
+library.  Importing this module loads ``libgd.so`` from the package directory and fails
+loudly when it is missing (build it with ``python -m paper_2408_01584_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgd.so")
+
+GD_OK, GD_E_ARG, GD_E_SIZE, GD_E_HIP, GD_E_STATE, GD_E_NONFINITE, GD_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "GD_OK", -1: "GD_E_ARG", -2: "GD_E_SIZE", -3: "GD_E_HIP", -4: "GD_E_STATE",
+                -5: "GD_E_NONFINITE", -6: "GD_E_UNSUPPORTED"}
+
+GD_FLAG_COLL_AGENT, GD_FLAG_COLL_EDGE, GD_FLAG_GOAL, GD_FLAG_DONE, GD_FLAG_ALIVE, GD_FLAG_VISIBLE = 1, 2, 4, 8, 16, 32
+GD_AUTO_RESET, GD_TERMINATE_ON_COLLISION, GD_CHECK_FINITE, GD_USE_GRAPH = 1, 2, 4, 8
+
+ENTRY_POINTS = ("gd_partner_slots", "gd_workspace_size", "gd_create", "gd_reset", "gd_step",
+                "gd_obs", "gd_rollout_fwd", "gd_rollout_bwd", "gd_check", "gd_destroy",
+                "gd_last_error")
+
+
+class GDError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class gd_config(C.Structure):
+    _fields_ = [("num_worlds", C.c_int32), ("top_k", C.c_int32), ("partners", C.c_int32),
+                ("episode_len", C.c_int32), ("lidar_rays", C.c_int32), ("flags", C.c_uint32),
+                ("dt", C.c_float), ("obs_radius", C.c_float), ("goal_radius", C.c_float),
+                ("v_max", C.c_float), ("lidar_range", C.c_float), ("collision_penalty", C.c_float),
+                ("cell_size", C.c_float), ("obs_waves", C.c_int32), ("obs_bins", C.c_int32),
+                ("obs_chunk", C.c_int32), ("reserved", C.c_int32 * 2)]
+
+
+_BUF_FIELDS = ("agent_off", "road_off", "x", "y", "yaw", "speed", "length", "width", "goal_x",
+               "goal_y", "road_x", "road_y", "road_dir", "road_meta", "obs_ego", "obs_partner",
+               "partner_mask", "obs_road", "road_idx", "lidar", "lidar_hit", "reward", "flags",
+               "world_done", "t", "workspace")
+
+
+class gd_buffers(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in _BUF_FIELDS] + [("workspace_bytes", C.c_size_t)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libgd.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libgd.so not found at %s: build it with "
+                               "`python -m paper_2408_01584_amd.build`" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64p, szp = C.c_void_p, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_size_t)
+        cfgp = C.POINTER(gd_config)
+        sig = {
+            "gd_partner_slots": [cfgp, vp, i64p],
+            "gd_workspace_size": [cfgp, vp, vp, szp],
+            "gd_create": [cfgp, vp, vp, C.POINTER(gd_buffers), vp, C.POINTER(vp)],
+            "gd_reset": [vp, vp, vp],
+            "gd_step": [vp, vp, vp],
+            "gd_obs": [vp, vp],
+            "gd_rollout_fwd": [vp, vp, i32, i32, vp, vp, vp],
+            "gd_rollout_bwd": [vp, vp, vp, i32, i32, vp, vp, vp, vp],
+            "gd_check": [vp, vp],
+            "gd_destroy": [vp],
+            "gd_last_error": [],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        L.gd_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def gd_last_error() -> str:
+    return lib().gd_last_error().decode()
+
+
+def _check(status: int) -> int:
+    if status != GD_OK:
+        raise GDError(status, gd_last_error())
+    return status
+
+
+def gd_partner_slots(cfg: gd_config, h_agent_off) -> int:
+    out = C.c_int64(0)
+    _check(lib().gd_partner_slots(C.byref(cfg), h_agent_off.ctypes.data, C.byref(out)))
+    return out.value
+
+
+def gd_workspace_size(cfg: gd_config, h_agent_off, h_road_off) -> int:
+    out = C.c_size_t(0)
+    _check(lib().gd_workspace_size(C.byref(cfg), h_agent_off.ctypes.data, h_road_off.ctypes.data,
+                                   C.byref(out)))
+    return out.value
+
+
+def gd_create(cfg: gd_config, h_agent_off, h_road_off, bufs: gd_buffers, stream: int):
+    h = C.c_void_p(0)
+    _check(lib().gd_create(C.byref(cfg), h_agent_off.ctypes.data, h_road_off.ctypes.data,
+                           C.byref(bufs), C.c_void_p(stream), C.byref(h)))
+    return h
+
+
+def gd_reset(sim, world_mask_ptr: int | None, stream: int):
+    _check(lib().gd_reset(sim, C.c_void_p(world_mask_ptr or 0), C.c_void_p(stream)))
+
+
+def gd_step(sim, actions_ptr: int, stream: int):
+    _check(lib().gd_step(sim, C.c_void_p(actions_ptr), C.c_void_p(stream)))
+
+
+def gd_obs(sim, stream: int):
+    _check(lib().gd_obs(sim, C.c_void_p(stream)))
+
+
+def gd_rollout_fwd(sim, actions_ptr: int, T: int, ckpt_every: int, rewards_ptr: int,
+                   ckpt_ptr: int, stream: int):
+    _check(lib().gd_rollout_fwd(sim, C.c_void_p(actions_ptr), T, ckpt_every,
+                                C.c_void_p(rewards_ptr), C.c_void_p(ckpt_ptr), C.c_void_p(stream)))
+
+
+def gd_rollout_bwd(sim, actions_ptr: int, ckpt_ptr: int, T: int, ckpt_every: int,
+                   grad_rewards_ptr: int, grad_actions_ptr: int, grad_state0_ptr: int | None,
+                   stream: int):
+    _check(lib().gd_rollout_bwd(sim, C.c_void_p(actions_ptr), C.c_void_p(ckpt_ptr), T, ckpt_every,
+                                C.c_void_p(grad_rewards_ptr), C.c_void_p(grad_actions_ptr),
+                                C.c_void_p(grad_state0_ptr or 0), C.c_void_p(stream)))
+
+
+def gd_check(sim, stream: int):
+    _check(lib().gd_check(sim, C.c_void_p(stream)))
+
+
+def gd_destroy(sim):
+    _check(lib().gd_destroy(sim))

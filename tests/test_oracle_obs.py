@@ -187,3 +187,24 @@ def test_lidar_wall_and_box(oracle_mod):
     assert r2["lidar"][0, 15] == 50.0 and r2["lidar_hit"][0, 15] == 0
     # seen from the second agent, the first is 17.75 m behind
     np.testing.assert_allclose(r2["lidar"][1, 15], 17.75, atol=1e-9)
+
+
+def test_partner_relative_heading_and_position(oracle_mod):
+    """Partner heading is yaw_j - yaw_i wrapped to [-pi, pi); its position is rotated
+    into agent i's frame (checked with complex arithmetic)."""
+    agents = [(1.0, 2.0, 0.2, 4.5, 2.0), (6.0, -3.0, 2.9, 4.0, 1.8), (-4.0, 5.0, -2.9, 4.5, 2.0)]
+    sc = tiny_world(agents, speeds=[1.0, 2.0, 3.0])
+    r = oracle_mod.OracleSim(sc).reset()
+    yaw = sc.yaw.astype(np.float64)
+    pos = sc.x.astype(np.float64) + 1j * sc.y.astype(np.float64)
+    for i in range(3):
+        others = [j for j in range(3) if j != i]
+        for s, j in enumerate(others):
+            f = r["partner"][i * 2 + s]
+            q = (pos[j] - pos[i]) * np.exp(-1j * yaw[i])
+            np.testing.assert_allclose(f[:2], [q.real, q.imag], atol=1e-12)
+            want = (yaw[j] - yaw[i] + np.pi) % (2 * np.pi) - np.pi
+            np.testing.assert_allclose(f[2], want, atol=1e-12)
+            assert f[3] == sc.speed[j] and f[4] == sc.length[j] and f[5] == sc.width[j]
+    # yaw difference 2.9 - (-2.9) = 5.8 wraps to 5.8 - 2 pi
+    np.testing.assert_allclose(r["partner"][2 * 2 + 1][2], 5.8 - 2 * np.pi, atol=1e-6)
