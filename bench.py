@@ -1,0 +1,201 @@
+#!/usr/bin/env python3
+"""Throughput of the batched driving-simulator step on one MI355X.
+
+Metric: agent steps per second (ASPS = S * sum_k |A_k| / dT, Sec. 4.1) of the full step
+(dynamics, collision, reward/done/auto-reset, ego + partner + road top-K observation).
+
+Default workload: 256 worlds x 64 agents, 4000 road points per world (seeded 3x3
+intersection grids on 100 m blocks), top-K 200 road points, 63 partner slots, radius
+50 m, dt 0.1 s, 91-step episodes with auto-reset, random actions.  Inputs are resident in
+HBM before the timed region; each step writes its observation into the next slot of a
+rollout ring larger than the 256 MB Infinity Cache, as a training loop would.
+
+Prints one JSON line.  `--gpus N` with N > 1 exits: this benchmark uses one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12  # MI355X HBM3E, B/s
+PMC_FILE = os.path.join(ROOT, "profiles", "road_obs_cfg1_counters.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=91)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--ring-mb", type=int, default=1536, help="observation ring size (MB)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for HBM counter calibration)")
+    return ap.parse_args()
+
+
+def source_digest(*names):
+    h = hashlib.sha256()
+    for n in names:
+        h.update(open(os.path.join(ROOT, "paper_2408_01584_amd", "csrc", n), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the simulator step shards by whole worlds with "
+              "no exchange between GPUs, and this build measures one GPU's share (--gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2408_01584_amd import scenes as S
+    from paper_2408_01584_amd.sim import Sim
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg_id = 1
+    scene = S.make_scene(cfg_id)
+    p = scene.params
+    A, W = scene.num_agents, scene.num_worlds
+    K, P = p.top_k, p.partners
+    sim = Sim(scene)
+    T = args.steps + args.warmup
+    actions = torch.as_tensor(S.make_actions(cfg_id, T, A), device=dev)
+
+    # observation ring (> Infinity Cache) so every step's writes reach HBM
+    Sl = sim.S
+    step_obs_bytes = A * 8 * 4 + Sl * 6 * 4 + Sl + A * K * 16 + A * K * 4
+    n_slots = max(2, math.ceil(args.ring_mb * 1e6 / step_obs_bytes))
+    ring = dict(ego=torch.empty((n_slots, A, 8), device=dev), partner=torch.empty((n_slots, Sl, 6), device=dev),
+                pmask=torch.empty((n_slots, Sl), dtype=torch.uint8, device=dev),
+                road=torch.empty((n_slots, A, K, 4), device=dev),
+                road_idx=torch.empty((n_slots, A, K), dtype=torch.int32, device=dev))
+
+    def bind(k):
+        s = k % n_slots
+        sim.set_obs_buffers(ring["ego"][s], ring["partner"][s], ring["pmask"][s], ring["road"][s],
+                            ring["road_idx"][s])
+
+    for k in range(args.warmup):
+        bind(k)
+        sim.step(actions[k])
+    torch.cuda.synchronize()
+    sim.get_timing()
+    sim.set_timing(True)
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for k in range(args.steps):
+        bind(args.warmup + k)
+        sim.step(actions[args.warmup + k])
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    phase_ms, phase_n = sim.get_timing()
+    sim.set_timing(False)
+
+    # controlled-agent (CASPS-like) share: agents observed per step, untimed replay
+    vis = 0
+    for k in range(min(args.steps, 91)):
+        sim.step(actions[k % T])
+        vis += int(((sim.buf["flags"] & 32) != 0).sum().item())
+    vis_frac = vis / (A * min(args.steps, 91))
+
+    value = A * args.steps / (ms / 1e3)
+    # dominant kernel: road radius filter + top-K; algorithmic bytes per agent:
+    #   writes 20 K (4 floats + 1 index per slot), reads the world's road once
+    #   (16 B per point: x, y, direction, type/index) and the agent's pose (13 B)
+    R_w = scene.num_road / W
+    unit_bytes = 20 * K + 16 * R_w / (A / W) + 13
+    launch_bytes = unit_bytes * A
+    road_ms = phase_ms[1] / max(phase_n[1], 1)
+    achieved = launch_bytes / (road_ms / 1e3)
+    traffic = None
+    if os.path.exists(PMC_FILE):
+        pm = json.load(open(PMC_FILE))
+        if pm.get("source_digest") == source_digest("gd_obs.hip", "gd_internal.h") and \
+                pm.get("workload") == "cfg1":
+            traffic = pm["hbm_bytes_per_launch"]
+    # whole step, algorithmic bytes per agent-step
+    step_unit = 64 + 32 + 25 * P + 20 * K + 16 * R_w / (A / W)
+    out = {
+        "metric": "agent-steps/sec (full step) on 1 MI355X",
+        "value": round(value, 1),
+        "unit": "agent-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "256 worlds x 64 agents, 4000 road points per world (3x3 intersection "
+                               "grid, 100 m blocks), top-K 200, 63 partners, radius 50 m, dt 0.1 s, "
+                               "91-step episodes with auto-reset, random actions",
+                   "worlds": W, "agents": A, "road_points_per_world": int(R_w), "top_k": K,
+                   "partners": P, "obs_ring_slots": n_slots},
+        "roofline": {"kernel": "k_road_obs", "bound": "hbm", "achieved": round(achieved / 1e9, 1),
+                     "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),
+                     "traffic": traffic, "algorithmic_bytes_per_launch": int(launch_bytes),
+                     "avg_launch_ms": round(road_ms, 5)},
+        "step": {"algorithmic_bytes_per_agent_step": round(step_unit, 1),
+                 "achieved_GBps": round(step_unit * A / (ms / args.steps / 1e3) / 1e9, 1),
+                 "hbm_frac": round(step_unit * A / (ms / args.steps / 1e3) / HBM_PEAK, 4),
+                 "phase_ms_per_step": {"world": round(phase_ms[0] / max(phase_n[0], 1), 5),
+                                       "road_obs": round(road_ms, 5)},
+                 "observed_agent_fraction": round(vis_frac, 4),
+                 "active_agent_steps_per_s": round(value * vis_frac, 1)},
+    }
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 2 * a.numel() * 4
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(cfg_id, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(cfg_id, steps):
+    """The FP64 oracle (plain C, OpenMP over worlds) on a bounded sample of the same
+    workload: all worlds for `steps` steps."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_2408_01584_amd import scenes as S
+    O.build(force=False)
+    scene = S.make_scene(cfg_id)
+    acts = S.make_actions(cfg_id, steps, scene.num_agents).astype(np.float64)
+    sim = O.OracleSim(scene)
+    sim.step(acts[0])  # warm
+    t = time.perf_counter()
+    for k in range(1, steps):
+        sim.step(acts[k])
+    dt = time.perf_counter() - t
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(scene.num_agents * (steps - 1) / dt, 1), "unit": "agent-steps/s",
+            "cores": cores, "kind": "oracle",
+            "sample": "all %d worlds of the workload for %d steps (FP64 C oracle, OpenMP over "
+                      "worlds, %.1f s wall)" % (scene.num_worlds, steps - 1, dt)}
+
+
+if __name__ == "__main__":
+    main()

@@ -214,6 +214,27 @@ gd_status gd_rollout_bwd(gd_sim *sim, const float *actions, const float *ckpt, i
                          int32_t ckpt_every, const float *grad_rewards, float *grad_actions,
                          float *grad_state0, void *stream);
 
+/* Re-point the observation outputs (obs_ego, obs_partner, partner_mask, obs_road,
+ * road_idx, lidar, lidar_hit; the other fields of `bufs` are ignored) so that the next
+ * calls write the observation straight into, e.g., step t of a caller's rollout buffer.
+ * Same shapes and NULL rules as in gd_create.  Takes effect for work enqueued after it. */
+gd_status gd_set_obs_buffers(gd_sim *sim, const gd_buffers *bufs);
+
+/* Kernel timing (tracing).  While enabled, gd_reset / gd_step / gd_obs / gd_rollout_*
+ * record a HIP event pair on the caller's stream around each kernel they launch.
+ * gd_get_timing waits for the recorded events, writes the summed milliseconds and the
+ * launch count of each phase (GD_PHASE_*) into ms[GD_NUM_PHASES] and
+ * count[GD_NUM_PHASES], and clears the record.  Events are host-side objects; no device
+ * memory is allocated. */
+#define GD_PHASE_WORLD 0      /* dynamics, collision, reward/done/reset, ego + partners */
+#define GD_PHASE_ROAD_OBS 1   /* road radius filter + top-K */
+#define GD_PHASE_LIDAR 2
+#define GD_PHASE_ROLLOUT_FWD 3
+#define GD_PHASE_ROLLOUT_BWD 4
+#define GD_NUM_PHASES 5
+gd_status gd_set_timing(gd_sim *sim, int32_t enable);
+gd_status gd_get_timing(gd_sim *sim, double *ms, int64_t *count);
+
 /* Synchronise `stream` and report asynchronous failures: GD_E_HIP for a device fault,
  * GD_E_NONFINITE when GD_CHECK_FINITE saw a NaN/Inf action since the last gd_check
  * (the word is then cleared). */

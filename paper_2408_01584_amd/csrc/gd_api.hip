@@ -15,7 +15,7 @@
 
 namespace gdk {
 hipError_t launch_road_obs_impl(const SimArgs &a, const ObsItem *items, int n_items, int waves,
-                                int bins, int max_road, hipStream_t s);
+                                int bins, int max_road, int max_agents, hipStream_t s);
 hipError_t launch_lidar_impl(const SimArgs &a, int max_agents, hipStream_t s);
 hipError_t launch_rollout_fwd_impl(const SimArgs &a, const float2 *actions, int T, int C,
                                    float *rewards, float *ckpt, hipStream_t s);
@@ -68,6 +68,11 @@ struct gd_sim {
     int waves = 8, bins = 256, chunk = 64;
     int max_road = 0, max_agents = 0;
     long long slots = 0;
+    // kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> events;
+    size_t events_used = 0;
+    std::vector<std::pair<size_t, int>> records;  // (first event index, phase)
     // graph mode
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -373,30 +378,61 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
     return GD_OK;
 }
 
-static gd_status enqueue_obs(gd_sim *sim, hipStream_t s) {
-    hipError_t e = launch_road_obs_impl(sim->args, sim->d_items, sim->n_items, sim->waves, sim->bins,
-                                        sim->max_road, s);
-    if (e != hipSuccess) return hip_fail(e, "road observation launch");
-    if (sim->args.N > 0) {
-        e = launch_lidar_impl(sim->args, sim->max_agents, s);
-        if (e != hipSuccess) return hip_fail(e, "lidar launch");
+// ---- optional event pair around each kernel (gd_set_timing)
+static hipError_t t_begin(gd_sim *sim, hipStream_t s, size_t &idx) {
+    if (!sim->timing) return hipSuccess;
+    while (sim->events_used + 2 > sim->events.size()) {
+        hipEvent_t ev;
+        hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) return e;
+        sim->events.push_back(ev);
     }
+    idx = sim->events_used;
+    sim->events_used += 2;
+    return hipEventRecord(sim->events[idx], s);
+}
+
+static hipError_t t_end(gd_sim *sim, hipStream_t s, size_t idx, int phase) {
+    if (!sim->timing) return hipSuccess;
+    sim->records.push_back({idx, phase});
+    return hipEventRecord(sim->events[idx + 1], s);
+}
+
+#define TIMED(sim, s, phase, launch_expr, what)                  \
+    do {                                                          \
+        size_t ti_ = 0;                                           \
+        hipError_t te_ = t_begin(sim, s, ti_);                    \
+        if (te_ != hipSuccess) return hip_fail(te_, "timing event"); \
+        hipError_t le_ = (launch_expr);                           \
+        if (le_ != hipSuccess) return hip_fail(le_, what);        \
+        te_ = t_end(sim, s, ti_, phase);                          \
+        if (te_ != hipSuccess) return hip_fail(te_, "timing event"); \
+    } while (0)
+
+static gd_status enqueue_obs(gd_sim *sim, hipStream_t s) {
+    if ((sim->args.K > 0 || sim->slots > 0) && sim->n_items > 0)
+        TIMED(sim, s, GD_PHASE_ROAD_OBS,
+              launch_road_obs_impl(sim->args, sim->d_items, sim->n_items, sim->waves, sim->bins,
+                                   sim->max_road, sim->max_agents, s),
+              "observation launch");
+    if (sim->args.N > 0 && sim->args.A > 0)
+        TIMED(sim, s, GD_PHASE_LIDAR, launch_lidar_impl(sim->args, sim->max_agents, s), "lidar launch");
     return GD_OK;
 }
 
 gd_status gd_reset(gd_sim *sim, const uint8_t *world_mask, void *stream) {
     if (!sim) return fail(GD_E_ARG, "sim is NULL");
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_world_step(sim->args, kModeReset, nullptr, world_mask, s);
-    if (e != hipSuccess) return hip_fail(e, "reset launch");
+    TIMED(sim, s, GD_PHASE_WORLD, launch_world_step(sim->args, kModeReset, nullptr, world_mask, s),
+          "reset launch");
     return enqueue_obs(sim, s);
 }
 
 gd_status gd_obs(gd_sim *sim, void *stream) {
     if (!sim) return fail(GD_E_ARG, "sim is NULL");
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_world_step(sim->args, kModeObs, nullptr, nullptr, s);
-    if (e != hipSuccess) return hip_fail(e, "obs launch");
+    TIMED(sim, s, GD_PHASE_WORLD, launch_world_step(sim->args, kModeObs, nullptr, nullptr, s),
+          "obs launch");
     return enqueue_obs(sim, s);
 }
 
@@ -404,8 +440,8 @@ gd_status gd_step(gd_sim *sim, const float *actions, void *stream) {
     if (!sim) return fail(GD_E_ARG, "sim is NULL");
     if (!actions && sim->args.A > 0) return fail(GD_E_ARG, "actions is NULL");
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = launch_world_step(sim->args, kModeStep, (const float2 *)actions, nullptr, s);
-    if (e != hipSuccess) return hip_fail(e, "step launch");
+    TIMED(sim, s, GD_PHASE_WORLD,
+          launch_world_step(sim->args, kModeStep, (const float2 *)actions, nullptr, s), "step launch");
     return enqueue_obs(sim, s);
 }
 
@@ -416,9 +452,10 @@ gd_status gd_rollout_fwd(gd_sim *sim, const float *actions, int32_t T, int32_t c
     if (ckpt_every < 1 || ckpt_every > 32) return fail(GD_E_ARG, "ckpt_every must be in [1, 32]");
     if (T == 0 || sim->args.A == 0) return GD_OK;
     if (!actions || !rewards || !ckpt) return fail(GD_E_ARG, "NULL buffer");
-    hipError_t e = launch_rollout_fwd_impl(sim->args, (const float2 *)actions, T, ckpt_every, rewards,
-                                           ckpt, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "rollout forward launch");
+    hipStream_t s = (hipStream_t)stream;
+    TIMED(sim, s, GD_PHASE_ROLLOUT_FWD,
+          launch_rollout_fwd_impl(sim->args, (const float2 *)actions, T, ckpt_every, rewards, ckpt, s),
+          "rollout forward launch");
     return GD_OK;
 }
 
@@ -430,10 +467,11 @@ gd_status gd_rollout_bwd(gd_sim *sim, const float *actions, const float *ckpt, i
     if (ckpt_every < 1 || ckpt_every > 32) return fail(GD_E_ARG, "ckpt_every must be in [1, 32]");
     if (T == 0 || sim->args.A == 0) return GD_OK;
     if (!actions || !ckpt || !grad_rewards || !grad_actions) return fail(GD_E_ARG, "NULL buffer");
-    hipError_t e = launch_rollout_bwd_impl(sim->args, (const float2 *)actions, ckpt, T, ckpt_every,
-                                           grad_rewards, (float2 *)grad_actions, grad_state0,
-                                           (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "rollout backward launch");
+    hipStream_t s = (hipStream_t)stream;
+    TIMED(sim, s, GD_PHASE_ROLLOUT_BWD,
+          launch_rollout_bwd_impl(sim->args, (const float2 *)actions, ckpt, T, ckpt_every, grad_rewards,
+                                  (float2 *)grad_actions, grad_state0, s),
+          "rollout backward launch");
     return GD_OK;
 }
 
@@ -451,8 +489,50 @@ gd_status gd_check(gd_sim *sim, void *stream) {
     return GD_OK;
 }
 
+gd_status gd_set_obs_buffers(gd_sim *sim, const gd_buffers *b) {
+    if (!sim || !b) return fail(GD_E_ARG, "NULL argument");
+    SimArgs &a = sim->args;
+    if (!b->obs_ego) return fail(GD_E_ARG, "buffer obs_ego is NULL");
+    if (sim->slots > 0 && (!b->obs_partner || !b->partner_mask)) return fail(GD_E_ARG, "partner buffers are NULL");
+    if (a.K > 0 && a.A > 0 && (!b->obs_road || !b->road_idx)) return fail(GD_E_ARG, "road obs buffers are NULL");
+    if (a.N > 0 && a.A > 0 && (!b->lidar || !b->lidar_hit)) return fail(GD_E_ARG, "lidar buffers are NULL");
+    a.ego = b->obs_ego;
+    a.partner = b->obs_partner;
+    a.pmask = b->partner_mask;
+    a.road = b->obs_road;
+    a.road_idx = b->road_idx;
+    a.lidar = b->lidar;
+    a.lidar_hit = b->lidar_hit;
+    return GD_OK;
+}
+
+gd_status gd_set_timing(gd_sim *sim, int32_t enable) {
+    if (!sim) return fail(GD_E_ARG, "sim is NULL");
+    sim->timing = enable != 0;
+    return GD_OK;
+}
+
+gd_status gd_get_timing(gd_sim *sim, double *ms, int64_t *count) {
+    if (!sim || !ms || !count) return fail(GD_E_ARG, "NULL argument");
+    for (int p = 0; p < GD_NUM_PHASES; p++) {
+        ms[p] = 0.0;
+        count[p] = 0;
+    }
+    for (auto &r : sim->records) {
+        HIP_TRY(hipEventSynchronize(sim->events[r.first + 1]), "event sync");
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, sim->events[r.first], sim->events[r.first + 1]), "event time");
+        ms[r.second] += t;
+        count[r.second] += 1;
+    }
+    sim->records.clear();
+    sim->events_used = 0;
+    return GD_OK;
+}
+
 gd_status gd_destroy(gd_sim *sim) {
     if (!sim) return GD_OK;
+    for (hipEvent_t ev : sim->events) (void)hipEventDestroy(ev);
     if (sim->graph_exec) (void)hipGraphExecDestroy(sim->graph_exec);
     if (sim->graph) (void)hipGraphDestroy(sim->graph);
     delete sim;

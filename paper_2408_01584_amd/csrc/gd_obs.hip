@@ -69,32 +69,51 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
 }
 
 template <int NB, bool STAGED>
-__global__ __launch_bounds__(1024) void k_road_obs(SimArgs a, const ObsItem *__restrict__ items,
-                                                   int road_cap) {
+__global__ __launch_bounds__(1024) void k_obs(SimArgs a, const ObsItem *__restrict__ items,
+                                              int road_cap, int agent_cap) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int BPL = NB / kWave;  // bins per lane
     const ObsItem it = items[blockIdx.x];
     const int w = it.w;
     const int r0 = a.road_off[w];
     const int nr = a.road_off[w + 1] - r0;
+    const int a0w = a.agent_off[w];
+    const int n = a.agent_off[w + 1] - a0w;
     const WorldGrid g = a.grid[w];
     const int nwaves = blockDim.x / kWave;
     const int wid = threadIdx.x / kWave;
     const int lane = threadIdx.x & (kWave - 1);
     const int K = a.K;
     const int scap = obs_scap(K);
+    const int S = a.P >= 0 ? a.P : (n > 0 ? n - 1 : 0);
 
+    // LDS: [road xy][world agents: x y yaw v L W flags][per-wave selection buffers]
     float2 *sroad = reinterpret_cast<float2 *>(smem);
-    unsigned char *mine = smem + (STAGED ? (size_t)road_cap * 8 : 0) + (size_t)wid * per_wave_bytes(NB, K);
+    float *sag = reinterpret_cast<float *>(smem + (STAGED ? (size_t)road_cap * 8 : 0));
+    float *sx = sag, *sy = sag + agent_cap, *syaw = sag + 2 * agent_cap, *sv = sag + 3 * agent_cap;
+    float *sL = sag + 4 * agent_cap, *sW = sag + 5 * agent_cap;
+    int *sf = reinterpret_cast<int *>(sag + 6 * agent_cap);
+    unsigned char *mine = reinterpret_cast<unsigned char *>(sag + 7 * agent_cap) +
+                          (size_t)wid * per_wave_bytes(NB, K);
     int *hstart = reinterpret_cast<int *>(mine);
     int *hcur = hstart + NB;
     uint2 *stage = reinterpret_cast<uint2 *>(hcur + NB);
     unsigned short *perm = reinterpret_cast<unsigned short *>(stage + scap);
 
-    if (STAGED) {
+    if (STAGED && K > 0)
         for (int k = threadIdx.x; k < nr; k += blockDim.x) sroad[k] = a.pt_xy[r0 + k];
-        __syncthreads();
-    }
+    if (S > 0)
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const int gi = a0w + i;
+            sx[i] = a.x[gi];
+            sy[i] = a.y[gi];
+            syaw[i] = a.yaw[gi];
+            sv[i] = a.v[gi];
+            sL[i] = a.len[gi];
+            sW[i] = a.wid[gi];
+            sf[i] = a.fl[gi];
+        }
+    __syncthreads();
     const float2 *rxy = STAGED ? sroad : (a.pt_xy + r0);
     const float2 *aux = a.pt_aux + r0;
     const int *cst = a.cell_start + (size_t)w * kCellStride;
@@ -103,26 +122,62 @@ __global__ __launch_bounds__(1024) void k_road_obs(SimArgs a, const ObsItem *__r
     const float marg = 1e-3f * g.cs + 1e-3f;
 
     for (int ai = it.a0 + wid; ai < it.a1; ai += nwaves) {
+        const int l = ai - a0w;
+        const uint8_t f = a.fl[ai];
+        const bool vis = (f & GD_FLAG_VISIBLE) != 0;
+        const float px = a.x[ai], py = a.y[ai], yaw = a.yaw[ai];
+        float sny, csy;
+        sincosf(yaw, &sny, &csy);
+
+        // ---- partners: lane = slot; slot s holds the s-th other agent in index order
+        if (S > 0) {
+            const long long base = a.P >= 0 ? (long long)ai * a.P : a.pbase[w] + (long long)l * S;
+            for (int s = lane; s < S; s += kWave) {
+                const int j = s < l ? s : s + 1;
+                float f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f, f4 = 0.f, f5 = 0.f;
+                uint8_t m = 0;
+                if (vis && j < n && (sf[j] & GD_FLAG_VISIBLE) &&
+                    key32(px, py, sx[j], sy[j]) <= R2) {
+                    float dx = sx[j] - px, dy = sy[j] - py;
+                    f0 = csy * dx + sny * dy;
+                    f1 = -sny * dx + csy * dy;
+                    f2 = wrap_pi(syaw[j] - yaw);
+                    f3 = sv[j];
+                    f4 = sL[j];
+                    f5 = sW[j];
+                    m = 1;
+                }
+                float2 *po = reinterpret_cast<float2 *>(a.partner + (size_t)(base + s) * 6);
+                po[0] = make_float2(f0, f1);
+                po[1] = make_float2(f2, f3);
+                po[2] = make_float2(f4, f5);
+                a.pmask[base + s] = m;
+            }
+        }
+        if (K == 0) continue;
+
         float4 *out = reinterpret_cast<float4 *>(a.road + (size_t)ai * K * 4);
         int *oidx = a.road_idx + (size_t)ai * K;
-        const uint8_t f = a.fl[ai];
-        if (!(f & GD_FLAG_VISIBLE)) {
+        if (!vis) {
             for (int s = lane; s < K; s += kWave) {
                 out[s] = make_float4(0.f, 0.f, 0.f, 0.f);
                 oidx[s] = -1;
             }
             continue;
         }
-        const float px = a.x[ai], py = a.y[ai], yaw = a.yaw[ai];
         for (int b = lane; b < NB; b += kWave) hcur[b] = 0;
-        wave_sync();
+        // candidate rows of the grid, one per lane (at most 64 rows per world)
         const int rlo = cell_coord(py - R, g.oy, g.inv_cs, g.ny);
         const int rhi = cell_coord(py + R, g.oy, g.inv_cs, g.ny);
+        const int nrows = rhi - rlo + 1;
+        int sq0 = 0, sq1 = 0;
+        if (lane < nrows) row_span(g, cst, rlo + lane, px, py, R, marg, sq0, sq1);
+        wave_sync();
 
         // ---- pass 1: histogram of bin(d2) over the candidates
-        for (int r = rlo; r <= rhi; r++) {
-            int q0, q1;
-            row_span(g, cst, r, px, py, R, marg, q0, q1);
+        for (int rr = 0; rr < nrows; rr++) {
+            const int q0 = __builtin_amdgcn_readlane(sq0, rr);
+            const int q1 = __builtin_amdgcn_readlane(sq1, rr);
             for (int base = q0; base < q1; base += kWave) {
                 int q = base + lane;
                 if (q < q1) {
@@ -181,9 +236,9 @@ __global__ __launch_bounds__(1024) void k_road_obs(SimArgs a, const ObsItem *__r
         const bool overflow = need > scap;
 
         // ---- pass 2: scatter the candidates of bins <= bstar, bin by bin
-        for (int r = rlo; r <= rhi; r++) {
-            int q0, q1;
-            row_span(g, cst, r, px, py, R, marg, q0, q1);
+        for (int rr = 0; rr < nrows; rr++) {
+            const int q0 = __builtin_amdgcn_readlane(sq0, rr);
+            const int q1 = __builtin_amdgcn_readlane(sq1, rr);
             for (int base = q0; base < q1; base += kWave) {
                 int q = base + lane;
                 if (q < q1) {
@@ -223,17 +278,15 @@ __global__ __launch_bounds__(1024) void k_road_obs(SimArgs a, const ObsItem *__r
             if (fin < K) perm[fin] = (unsigned short)p;
         }
 
-        float sy, cy;
-        sincosf(yaw, &sy, &cy);
         if (overflow) {
             // the cut bin is too large to stage: take its members one at a time
             unsigned long long prev = 0ull;
             bool first = true;
             for (int s = cut_start; s < K; s++) {
                 unsigned long long best = ~0ull;
-                for (int r = rlo; r <= rhi; r++) {
-                    int q0, q1;
-                    row_span(g, cst, r, px, py, R, marg, q0, q1);
+                for (int rr = 0; rr < nrows; rr++) {
+                    const int q0 = __builtin_amdgcn_readlane(sq0, rr);
+                    const int q1 = __builtin_amdgcn_readlane(sq1, rr);
                     for (int base = q0; base < q1; base += kWave) {
                         int q = base + lane;
                         if (q < q1) {
@@ -251,12 +304,11 @@ __global__ __launch_bounds__(1024) void k_road_obs(SimArgs a, const ObsItem *__r
                 best = wave_min_u64(best);
                 prev = best;
                 first = false;
-                // locate the element (x, y from the original arrays by its index)
                 if (lane == 0) {
                     int idx = (int)(best & 0xffffffu);
                     float qx = a.rx[r0 + idx], qy = a.ry[r0 + idx];
                     float dx = qx - px, dy = qy - py;
-                    out[s] = make_float4(cy * dx + sy * dy, -sy * dx + cy * dy,
+                    out[s] = make_float4(csy * dx + sny * dy, -sny * dx + csy * dy,
                                          wrap_pi(a.rdir[r0 + idx] - yaw),
                                          (float)(a.rmeta[r0 + idx] & 0xff));
                     oidx[s] = idx;
@@ -274,7 +326,7 @@ __global__ __launch_bounds__(1024) void k_road_obs(SimArgs a, const ObsItem *__r
                 float2 x2 = aux[e.y];
                 int bits = __float_as_int(x2.y);
                 float dx = p.x - px, dy = p.y - py;
-                out[s] = make_float4(cy * dx + sy * dy, -sy * dx + cy * dy, wrap_pi(x2.x - yaw),
+                out[s] = make_float4(csy * dx + sny * dy, -sny * dx + csy * dy, wrap_pi(x2.x - yaw),
                                      (float)((unsigned)bits >> 24));
                 oidx[s] = bits & 0xffffff;
             } else if (s >= nsel) {
@@ -286,38 +338,46 @@ __global__ __launch_bounds__(1024) void k_road_obs(SimArgs a, const ObsItem *__r
     }
 }
 
-size_t road_obs_lds_bytes(int waves, int bins, int K, int max_road) {
-    return (size_t)max_road * 8 + (size_t)waves * per_wave_bytes(bins, K);
+static size_t obs_lds_bytes(int waves, int bins, int K, int road_cap, int agent_cap) {
+    return (size_t)road_cap * 8 + (size_t)agent_cap * 28 + (size_t)waves * per_wave_bytes(bins, K);
+}
+
+template <int NB, bool STAGED>
+static hipError_t launch_one(const SimArgs &a, const ObsItem *items, int n_items, int waves,
+                             int road_cap, int agent_cap, hipStream_t s) {
+    size_t lds = obs_lds_bytes(waves, NB, a.K, road_cap, agent_cap);
+    auto kern = k_obs<NB, STAGED>;
+    static bool attr_set = false;  // per instantiation; the attribute allows the LDS maximum
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(n_items), dim3(waves * kWave), lds, s, a, items, road_cap, agent_cap);
+    return hipGetLastError();
 }
 
 template <int NB>
 static hipError_t launch_nb(const SimArgs &a, const ObsItem *items, int n_items, int waves,
-                            int max_road, bool staged, hipStream_t s) {
-    size_t lds = (staged ? (size_t)max_road * 8 : 0) + (size_t)waves * per_wave_bytes(NB, a.K);
-    if (staged) {
-        auto kern = k_road_obs<NB, true>;
-        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, dim3(n_items), dim3(waves * kWave), lds, s, a, items, max_road);
-    } else {
-        auto kern = k_road_obs<NB, false>;
-        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(kern, dim3(n_items), dim3(waves * kWave), lds, s, a, items, 0);
-    }
-    return hipGetLastError();
+                            int max_road, int max_agents, hipStream_t s) {
+    const size_t lds_cap = 160 * 1024;
+    const int S_any = a.P != 0;
+    const int agent_cap = S_any ? max_agents : 0;
+    if (a.K > 0 && obs_lds_bytes(waves, NB, a.K, max_road, agent_cap) <= lds_cap)
+        return launch_one<NB, true>(a, items, n_items, waves, max_road, agent_cap, s);
+    if (obs_lds_bytes(waves, NB, a.K, 0, agent_cap) > lds_cap) return hipErrorInvalidConfiguration;
+    return launch_one<NB, false>(a, items, n_items, waves, 0, agent_cap, s);
 }
 
 hipError_t launch_road_obs_impl(const SimArgs &a, const ObsItem *items, int n_items, int waves,
-                                int bins, int max_road, hipStream_t s) {
-    if (n_items <= 0 || a.K <= 0) return hipSuccess;
-    const size_t lds_cap = 160 * 1024;
-    bool staged = road_obs_lds_bytes(waves, bins, a.K, max_road) <= lds_cap;
+                                int bins, int max_road, int max_agents, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
     switch (bins) {
-        case 64: return launch_nb<64>(a, items, n_items, waves, max_road, staged, s);
-        case 128: return launch_nb<128>(a, items, n_items, waves, max_road, staged, s);
-        case 512: return launch_nb<512>(a, items, n_items, waves, max_road, staged, s);
-        default: return launch_nb<256>(a, items, n_items, waves, max_road, staged, s);
+        case 64: return launch_nb<64>(a, items, n_items, waves, max_road, max_agents, s);
+        case 128: return launch_nb<128>(a, items, n_items, waves, max_road, max_agents, s);
+        case 512: return launch_nb<512>(a, items, n_items, waves, max_road, max_agents, s);
+        default: return launch_nb<256>(a, items, n_items, waves, max_road, max_agents, s);
     }
 }
 

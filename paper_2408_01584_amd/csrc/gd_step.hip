@@ -1,5 +1,5 @@
 // Per-world part of the step: bicycle dynamics, agent/agent and agent/road-edge
-// collision, goal / reward / done, auto-reset, and the ego and partner observations.
+// collision, goal / reward / done, auto-reset, and the ego observation.
 //
 // One workgroup per world.  A world's agents (at most GD_MAX_AGENTS_PER_WORLD) are
 // staged in LDS so the all-pairs collision test and the partner features read them from
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(kStepThreads) void k_world_step(SimArgs a, int mode
     if (tid == 0) a.t[w] = t;
     __syncthreads();
 
-    // ---- observations of the resulting state (ego + partners)
+    // ---- ego observation of the resulting state
     if (mode != kModeStep || do_reset) {
         // state in LDS may be stale (obs-only, reset)
         for (int i = tid; i < n; i += kStepThreads) {
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kStepThreads) void k_world_step(SimArgs a, int mode
             sincosf(yaw, &sn, &cs);
             sc[i] = cs;
             ss[i] = sn;
-            if (mode == kModeObs) sf[i] = a.fl[gi];
+            if (!do_reset) sf[i] = a.fl[gi];  // obs-only, or a reset call that skips this world
         }
         __syncthreads();
     }
@@ -258,35 +258,6 @@ __global__ __launch_bounds__(kStepThreads) void k_world_step(SimArgs a, int mode
         float4 *eo = reinterpret_cast<float4 *>(a.ego + (size_t)gi * 8);
         eo[0] = e0;
         eo[1] = e1;
-    }
-    // partners: one thread per (agent, slot); a world's slots are one contiguous block
-    const int S = a.P >= 0 ? a.P : (n > 0 ? n - 1 : 0);
-    const long long base = a.P >= 0 ? (long long)a0 * a.P : a.pbase[w];
-    const int total = n * S;
-    for (int e = tid; e < total; e += kStepThreads) {
-        const int i = e / S;
-        const int s = e - i * S;
-        const int j = s < i ? s : s + 1;
-        float f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f, f4 = 0.f, f5 = 0.f;
-        uint8_t m = 0;
-        if (j < n && (sf[i] & GD_FLAG_VISIBLE) && (sf[j] & GD_FLAG_VISIBLE)) {
-            const float xi = sx[i], yi = sy[i];
-            if (key32(xi, yi, sx[j], sy[j]) <= a.R2_obs) {
-                float dx = sx[j] - xi, dy = sy[j] - yi;
-                f0 = sc[i] * dx + ss[i] * dy;
-                f1 = -ss[i] * dx + sc[i] * dy;
-                f2 = wrap_pi(syaw[j] - syaw[i]);
-                f3 = sv[j];
-                f4 = sL[j];
-                f5 = sW[j];
-                m = 1;
-            }
-        }
-        float2 *po = reinterpret_cast<float2 *>(a.partner + (size_t)(base + e) * 6);
-        po[0] = make_float2(f0, f1);
-        po[1] = make_float2(f2, f3);
-        po[2] = make_float2(f4, f5);
-        a.pmask[base + e] = m;
     }
 }
 

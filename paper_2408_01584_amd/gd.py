@@ -20,8 +20,10 @@ GD_FLAG_COLL_AGENT, GD_FLAG_COLL_EDGE, GD_FLAG_GOAL, GD_FLAG_DONE, GD_FLAG_ALIVE
 GD_AUTO_RESET, GD_TERMINATE_ON_COLLISION, GD_CHECK_FINITE, GD_USE_GRAPH = 1, 2, 4, 8
 
 ENTRY_POINTS = ("gd_partner_slots", "gd_workspace_size", "gd_create", "gd_reset", "gd_step",
-                "gd_obs", "gd_rollout_fwd", "gd_rollout_bwd", "gd_check", "gd_destroy",
-                "gd_last_error")
+                "gd_obs", "gd_rollout_fwd", "gd_rollout_bwd", "gd_set_obs_buffers", "gd_set_timing",
+                "gd_get_timing", "gd_check", "gd_destroy", "gd_last_error")
+GD_PHASE_WORLD, GD_PHASE_ROAD_OBS, GD_PHASE_LIDAR, GD_PHASE_ROLLOUT_FWD, GD_PHASE_ROLLOUT_BWD = range(5)
+GD_NUM_PHASES = 5
 
 
 class GDError(RuntimeError):
@@ -71,6 +73,9 @@ def lib():
             "gd_obs": [vp, vp],
             "gd_rollout_fwd": [vp, vp, i32, i32, vp, vp, vp],
             "gd_rollout_bwd": [vp, vp, vp, i32, i32, vp, vp, vp, vp],
+            "gd_set_obs_buffers": [vp, C.POINTER(gd_buffers)],
+            "gd_set_timing": [vp, i32],
+            "gd_get_timing": [vp, vp, vp],
             "gd_check": [vp, vp],
             "gd_destroy": [vp],
             "gd_last_error": [],
@@ -138,6 +143,22 @@ def gd_rollout_bwd(sim, actions_ptr: int, ckpt_ptr: int, T: int, ckpt_every: int
     _check(lib().gd_rollout_bwd(sim, C.c_void_p(actions_ptr), C.c_void_p(ckpt_ptr), T, ckpt_every,
                                 C.c_void_p(grad_rewards_ptr), C.c_void_p(grad_actions_ptr),
                                 C.c_void_p(grad_state0_ptr or 0), C.c_void_p(stream)))
+
+
+def gd_set_obs_buffers(sim, bufs: gd_buffers):
+    _check(lib().gd_set_obs_buffers(sim, C.byref(bufs)))
+
+
+def gd_set_timing(sim, enable: bool):
+    _check(lib().gd_set_timing(sim, 1 if enable else 0))
+
+
+def gd_get_timing(sim):
+    """(ms[GD_NUM_PHASES], count[GD_NUM_PHASES]) accumulated since the last call."""
+    ms = (C.c_double * GD_NUM_PHASES)()
+    cnt = (C.c_int64 * GD_NUM_PHASES)()
+    _check(lib().gd_get_timing(sim, C.cast(ms, C.c_void_p), C.cast(cnt, C.c_void_p)))
+    return list(ms), list(cnt)
 
 
 def gd_check(sim, stream: int):

@@ -118,6 +118,21 @@ class Sim:
     def obs(self):
         G.gd_obs(self.handle, _stream())
 
+    def set_obs_buffers(self, ego, partner, pmask, road, road_idx, lidar=None, lidar_hit=None):
+        """Write the next observations into these tensors (e.g. a slot of a rollout ring)."""
+        b = G.gd_buffers()
+        b.obs_ego, b.obs_partner, b.partner_mask = ego.data_ptr(), partner.data_ptr(), pmask.data_ptr()
+        b.obs_road, b.road_idx = road.data_ptr(), road_idx.data_ptr()
+        if lidar is not None:
+            b.lidar, b.lidar_hit = lidar.data_ptr(), lidar_hit.data_ptr()
+        G.gd_set_obs_buffers(self.handle, b)
+
+    def set_timing(self, enable: bool):
+        G.gd_set_timing(self.handle, enable)
+
+    def get_timing(self):
+        return G.gd_get_timing(self.handle)
+
     def check(self):
         G.gd_check(self.handle, _stream())
 
