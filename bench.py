@@ -37,6 +37,7 @@ def parse():
     ap.add_argument("--ring-mb", type=int, default=1536, help="observation ring size (MB)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--no-graph", action="store_true", help="launch kernels directly, no HIP graph")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
     return ap.parse_args()
@@ -69,7 +70,7 @@ def main():
     p = scene.params
     A, W = scene.num_agents, scene.num_worlds
     K, P = p.top_k, p.partners
-    sim = Sim(scene)
+    sim = Sim(scene, graph=not args.no_graph)
     T = args.steps + args.warmup
     actions = torch.as_tensor(S.make_actions(cfg_id, T, A), device=dev)
 
@@ -115,22 +116,22 @@ def main():
     vis_frac = vis / (A * min(args.steps, 91))
 
     value = A * args.steps / (ms / 1e3)
-    # dominant kernel: road radius filter + top-K; algorithmic bytes per agent:
-    #   writes 20 K (4 floats + 1 index per slot), reads the world's road once
-    #   (16 B per point: x, y, direction, type/index) and the agent's pose (13 B)
+    # the fused step kernel; algorithmic bytes per agent-step:
+    #   state read + write 32, length/width/goal 16, action 8, flags 2, reward 4, ego 32,
+    #   partners 25 P (24 B features + mask), road observation 20 K (16 B row + index),
+    #   the world's road read once (16 B per point: x, y, direction, type)
     R_w = scene.num_road / W
-    unit_bytes = 20 * K + 16 * R_w / (A / W) + 13
+    A_w = A / W
+    unit_bytes = 32 + 16 + 8 + 2 + 4 + 32 + 25 * P + 20 * K + 16 * R_w / A_w
     launch_bytes = unit_bytes * A
-    road_ms = phase_ms[1] / max(phase_n[1], 1)
-    achieved = launch_bytes / (road_ms / 1e3)
+    step_ms = phase_ms[0] / max(phase_n[0], 1)
+    achieved = launch_bytes / (step_ms / 1e3)
     traffic = None
     if os.path.exists(PMC_FILE):
         pm = json.load(open(PMC_FILE))
-        if pm.get("source_digest") == source_digest("gd_obs.hip", "gd_internal.h") and \
+        if pm.get("source_digest") == source_digest("gd_step.hip", "gd_internal.h") and \
                 pm.get("workload") == "cfg1":
             traffic = pm["hbm_bytes_per_launch"]
-    # whole step, algorithmic bytes per agent-step
-    step_unit = 64 + 32 + 25 * P + 20 * K + 16 * R_w / (A / W)
     out = {
         "metric": "agent-steps/sec (full step) on 1 MI355X",
         "value": round(value, 1),
@@ -149,15 +150,13 @@ def main():
                                "91-step episodes with auto-reset, random actions",
                    "worlds": W, "agents": A, "road_points_per_world": int(R_w), "top_k": K,
                    "partners": P, "obs_ring_slots": n_slots},
-        "roofline": {"kernel": "k_road_obs", "bound": "hbm", "achieved": round(achieved / 1e9, 1),
+        "roofline": {"kernel": "k_step", "bound": "hbm", "achieved": round(achieved / 1e9, 1),
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": round(achieved / HBM_PEAK, 4),
                      "traffic": traffic, "algorithmic_bytes_per_launch": int(launch_bytes),
-                     "avg_launch_ms": round(road_ms, 5)},
-        "step": {"algorithmic_bytes_per_agent_step": round(step_unit, 1),
-                 "achieved_GBps": round(step_unit * A / (ms / args.steps / 1e3) / 1e9, 1),
-                 "hbm_frac": round(step_unit * A / (ms / args.steps / 1e3) / HBM_PEAK, 4),
-                 "phase_ms_per_step": {"world": round(phase_ms[0] / max(phase_n[0], 1), 5),
-                                       "road_obs": round(road_ms, 5)},
+                     "bytes_per_agent_step": round(unit_bytes, 1), "avg_launch_ms": round(step_ms, 5)},
+        "step": {"end_to_end_GBps": round(launch_bytes / (ms / args.steps / 1e3) / 1e9, 1),
+                 "end_to_end_hbm_frac": round(launch_bytes / (ms / args.steps / 1e3) / HBM_PEAK, 4),
+                 "graph": not args.no_graph,
                  "observed_agent_fraction": round(vis_frac, 4),
                  "active_agent_steps_per_s": round(value * vis_frac, 1)},
     }

@@ -98,11 +98,13 @@ typedef struct {
     float lidar_range;         /* LIDAR range (m) > 0 when lidar_rays > 0 */
     float collision_penalty;   /* reward -= penalty when the agent collided */
     float cell_size;           /* road grid cell (m); 0 = library default (10 m) */
-    int32_t obs_waves;         /* launch shape of the observation kernel: waves per
-                                  workgroup (1, 2, 4, 8, 16; 0 = default) */
+    int32_t obs_waves;         /* launch shape of the step kernel: waves per workgroup
+                                  (1, 2, 4, 8, 12, 16; 0 = default 16, reduced until the
+                                  workgroup fits the LDS) */
     int32_t obs_bins;          /* distance bins of the top-K selection (64, 128, 256,
                                   512; 0 = default) */
-    int32_t obs_chunk;         /* agents per observation work item (0 = default) */
+    int32_t obs_cands;         /* candidate-list entries per wave of the top-K selection
+                                  (0 = default 1024; agents with more candidates rescan) */
     int32_t reserved[2];       /* must be zero */
 } gd_config;
 
@@ -226,12 +228,12 @@ gd_status gd_set_obs_buffers(gd_sim *sim, const gd_buffers *bufs);
  * launch count of each phase (GD_PHASE_*) into ms[GD_NUM_PHASES] and
  * count[GD_NUM_PHASES], and clears the record.  Events are host-side objects; no device
  * memory is allocated. */
-#define GD_PHASE_WORLD 0      /* dynamics, collision, reward/done/reset, ego + partners */
-#define GD_PHASE_ROAD_OBS 1   /* road radius filter + top-K */
-#define GD_PHASE_LIDAR 2
-#define GD_PHASE_ROLLOUT_FWD 3
-#define GD_PHASE_ROLLOUT_BWD 4
-#define GD_NUM_PHASES 5
+#define GD_PHASE_STEP 0       /* fused step: dynamics, collision, reward/done/reset, ego,
+                                 partner and road observations (a graph launch in graph mode) */
+#define GD_PHASE_LIDAR 1
+#define GD_PHASE_ROLLOUT_FWD 2
+#define GD_PHASE_ROLLOUT_BWD 3
+#define GD_NUM_PHASES 4
 gd_status gd_set_timing(gd_sim *sim, int32_t enable);
 gd_status gd_get_timing(gd_sim *sim, double *ms, int64_t *count);
 

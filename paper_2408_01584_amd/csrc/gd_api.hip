@@ -1,6 +1,7 @@
 // Host side of libgd.so: the C-ABI declared in include/gd.h.  Validates arguments,
-// lays out the caller's workspace, orders the observation work items (longest first),
-// and enqueues the kernels on the caller's stream.  No device memory is allocated here.
+// lays out the caller's workspace, chooses the launch shape of the fused step kernel,
+// orders the worlds longest-first, and enqueues kernels (or a captured HIP graph) on the
+// caller's stream.  No device memory is allocated here.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,18 +15,19 @@
 #include "gd_internal.h"
 
 namespace gdk {
-hipError_t launch_road_obs_impl(const SimArgs &a, const ObsItem *items, int n_items, int waves,
-                                int bins, int max_road, int max_agents, hipStream_t s);
 hipError_t launch_lidar_impl(const SimArgs &a, int max_agents, hipStream_t s);
 hipError_t launch_rollout_fwd_impl(const SimArgs &a, const float2 *actions, int T, int C,
                                    float *rewards, float *ckpt, hipStream_t s);
 hipError_t launch_rollout_bwd_impl(const SimArgs &a, const float2 *actions, const float *ckpt,
                                    int T, int C, const float *grad_rewards, float2 *grad_actions,
                                    float *grad_state0, hipStream_t s);
+bool step_kernel_node(const SimArgs *a, const StepCtl *c, int waves, int bins,
+                      hipKernelNodeParams &p, void **args);
+bool lidar_kernel_node(const SimArgs *a, int max_agents, hipKernelNodeParams &p, void **args);
 
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-Layout make_layout(int W, long long A, long long R, long long n_items) {
+Layout make_layout(int W, long long A, long long R) {
     Layout L{};
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -43,7 +45,7 @@ Layout make_layout(int W, long long A, long long R, long long n_items) {
     L.snap = take(sizeof(float4) * (size_t)A);
     L.pbase = take(sizeof(long long) * (size_t)W);
     L.err = take(256);
-    L.items = take(sizeof(ObsItem) * (size_t)n_items);
+    L.order = take(sizeof(int) * (size_t)W);
     L.total = off;
     return L;
 }
@@ -63,9 +65,8 @@ struct gd_sim {
     SimArgs args;
     std::vector<int32_t> h_agent_off, h_road_off;
     Layout lay;
-    ObsItem *d_items = nullptr;
-    int n_items = 0;
-    int waves = 8, bins = 256, chunk = 64;
+    StepCtl ctl{};  // launch shape of the fused step (mode and pointers set per call)
+    int waves = 16, bins = 256;
     int max_road = 0, max_agents = 0;
     long long slots = 0;
     // kernel timing
@@ -73,11 +74,12 @@ struct gd_sim {
     std::vector<hipEvent_t> events;
     size_t events_used = 0;
     std::vector<std::pair<size_t, int>> records;  // (first event index, phase)
-    // graph mode
+    // graph mode: one step kernel node (+ LIDAR node), re-pointed when buffers change
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
-    hipGraphNode_t step_node = nullptr;
-    const void *graph_actions = nullptr;
+    hipGraphNode_t step_node = nullptr, lidar_node = nullptr;
+    SimArgs graph_args{};
+    StepCtl graph_ctl{};
 };
 
 static thread_local std::string g_err;
@@ -96,9 +98,9 @@ static gd_status hip_fail(hipError_t e, const char *what) {
     return fail(GD_E_HIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
 }
 
-#define HIP_TRY(expr, what)                      \
-    do {                                         \
-        hipError_t e_ = (expr);                  \
+#define HIP_TRY(expr, what)                              \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
         if (e_ != hipSuccess) return hip_fail(e_, what); \
     } while (0)
 
@@ -114,19 +116,21 @@ static gd_status check_config(const gd_config *c, const int32_t *h_agent_off,
     if (c->lidar_rays < 0 || c->lidar_rays > GD_MAX_LIDAR_RAYS)
         return fail(GD_E_SIZE, "lidar_rays must be in [0, %d]", GD_MAX_LIDAR_RAYS);
     if (!(c->dt > 0.f) || !std::isfinite(c->dt)) return fail(GD_E_ARG, "dt must be > 0");
-    if (!(c->obs_radius > 0.f) || !std::isfinite(c->obs_radius)) return fail(GD_E_ARG, "obs_radius must be > 0");
-    if (!(c->goal_radius >= 0.f) || !std::isfinite(c->goal_radius)) return fail(GD_E_ARG, "goal_radius must be >= 0");
+    if (!(c->obs_radius > 0.f) || !std::isfinite(c->obs_radius))
+        return fail(GD_E_ARG, "obs_radius must be > 0");
+    if (!(c->goal_radius >= 0.f) || !std::isfinite(c->goal_radius))
+        return fail(GD_E_ARG, "goal_radius must be >= 0");
     if (!(c->v_max > 0.f)) return fail(GD_E_ARG, "v_max must be > 0");
     if (c->lidar_rays > 0 && !(c->lidar_range > 0.f)) return fail(GD_E_ARG, "lidar_range must be > 0");
     if (!std::isfinite(c->collision_penalty)) return fail(GD_E_ARG, "collision_penalty must be finite");
     if (!(c->cell_size >= 0.f) || !std::isfinite(c->cell_size)) return fail(GD_E_ARG, "cell_size must be >= 0");
     if (!(c->obs_waves == 0 || c->obs_waves == 1 || c->obs_waves == 2 || c->obs_waves == 4 ||
-          c->obs_waves == 8 || c->obs_waves == 16))
-        return fail(GD_E_ARG, "obs_waves must be 0, 1, 2, 4, 8 or 16");
+          c->obs_waves == 8 || c->obs_waves == 12 || c->obs_waves == 16))
+        return fail(GD_E_ARG, "obs_waves must be 0, 1, 2, 4, 8, 12 or 16");
     if (!(c->obs_bins == 0 || c->obs_bins == 64 || c->obs_bins == 128 || c->obs_bins == 256 ||
           c->obs_bins == 512))
         return fail(GD_E_ARG, "obs_bins must be 0, 64, 128, 256 or 512");
-    if (c->obs_chunk < 0) return fail(GD_E_ARG, "obs_chunk must be >= 0");
+    if (c->obs_cands < 0 || c->obs_cands > 4096) return fail(GD_E_ARG, "obs_cands must be in [0, 4096]");
     if (c->reserved[0] || c->reserved[1]) return fail(GD_E_ARG, "reserved fields must be zero");
     const int W = c->num_worlds;
     if (h_agent_off[0] != 0 || h_road_off[0] != 0) return fail(GD_E_ARG, "offsets must start at 0");
@@ -151,43 +155,117 @@ static long long partner_slots_of(const gd_config *c, const int32_t *h_agent_off
     return s;
 }
 
-static void launch_shape(const gd_config *c, int &waves, int &bins, int &chunk) {
-    waves = c->obs_waves ? c->obs_waves : 8;
+// Launch shape of the fused step: waves per workgroup, distance bins, LDS staging of the
+// road and size of the per-wave candidate list, shrunk until a workgroup fits the LDS.
+static bool launch_shape(const gd_config *c, int max_road, int max_agents, int &waves, int &bins,
+                         int &road_cap, int &cand_cap) {
     bins = c->obs_bins ? c->obs_bins : 256;
-    chunk = c->obs_chunk ? c->obs_chunk : 64;
-}
-
-// observation work items: chunks of one world's agents, costliest first (LPT order, so the
-// hardware dispatcher's in-order assignment acts as a longest-processing-time schedule)
-static std::vector<ObsItem> make_items(const gd_config *c, const int32_t *ao, const int32_t *ro,
-                                       int chunk) {
-    struct Rec {
-        ObsItem it;
-        double cost;
-    };
-    std::vector<Rec> v;
-    for (int w = 0; w < c->num_worlds; w++) {
-        int n = ao[w + 1] - ao[w];
-        double nr = ro[w + 1] - ro[w];
-        for (int s = 0; s < n; s += chunk) {
-            int e = std::min(n, s + chunk);
-            v.push_back({{w, ao[w] + s, ao[w] + e, 0}, (double)(e - s) * (nr + 256.0)});
+    const int want_waves = c->obs_waves ? c->obs_waves : 16;
+    const int want_cands = c->obs_cands ? c->obs_cands : 1024;
+    const int K = c->top_k;
+    const int agent_cap = std::max(max_agents, 1);
+    for (int staged = 1; staged >= 0; staged--) {
+        if (staged && K == 0) continue;
+        road_cap = staged ? std::max(max_road, 1) : 0;
+        for (int cc = want_cands; cc >= 128; cc /= 2) {
+            for (int wv = want_waves; wv >= 1; wv = (wv > 8 ? wv - 4 : wv / 2)) {
+                if (step_lds_bytes(wv, bins, K, K ? cc : 0, road_cap, agent_cap) <= (size_t)kLdsBytes) {
+                    waves = wv;
+                    cand_cap = K ? cc : 0;
+                    return true;
+                }
+            }
         }
     }
-    std::stable_sort(v.begin(), v.end(), [](const Rec &x, const Rec &y) { return x.cost > y.cost; });
-    std::vector<ObsItem> out;
-    out.reserve(v.size());
-    for (auto &r : v) out.push_back(r.it);
-    return out;
+    return false;
 }
 
-static long long n_items_of(const gd_config *c, const int32_t *ao, int chunk) {
-    long long k = 0;
-    for (int w = 0; w < c->num_worlds; w++) {
-        int n = ao[w + 1] - ao[w];
-        k += (n + chunk - 1) / chunk;
+// workgroup order: costliest worlds first, so that the in-order dispatch of workgroups
+// acts as a longest-processing-time-first schedule over the compute units
+static std::vector<int> world_order(int W, const int32_t *ao, const int32_t *ro) {
+    std::vector<int> ord(W);
+    std::vector<double> cost(W);
+    for (int w = 0; w < W; w++) {
+        ord[w] = w;
+        double n = ao[w + 1] - ao[w], r = ro[w + 1] - ro[w];
+        cost[w] = n * (r + 256.0) + n * n;
     }
-    return k;
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return cost[x] > cost[y]; });
+    return ord;
+}
+
+// ---- optional event pair around each kernel (gd_set_timing)
+static hipError_t t_begin(gd_sim *sim, hipStream_t s, size_t &idx) {
+    if (!sim->timing) return hipSuccess;
+    while (sim->events_used + 2 > sim->events.size()) {
+        hipEvent_t ev;
+        hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) return e;
+        sim->events.push_back(ev);
+    }
+    idx = sim->events_used;
+    sim->events_used += 2;
+    return hipEventRecord(sim->events[idx], s);
+}
+
+static hipError_t t_end(gd_sim *sim, hipStream_t s, size_t idx, int phase) {
+    if (!sim->timing) return hipSuccess;
+    sim->records.push_back({idx, phase});
+    return hipEventRecord(sim->events[idx + 1], s);
+}
+
+#define TIMED(sim, s, phase, launch_expr, what)                      \
+    do {                                                             \
+        size_t ti_ = 0;                                              \
+        hipError_t te_ = t_begin(sim, s, ti_);                       \
+        if (te_ != hipSuccess) return hip_fail(te_, "timing event"); \
+        hipError_t le_ = (launch_expr);                              \
+        if (le_ != hipSuccess) return hip_fail(le_, what);           \
+        te_ = t_end(sim, s, ti_, phase);                             \
+        if (te_ != hipSuccess) return hip_fail(te_, "timing event"); \
+    } while (0)
+
+static gd_status enqueue_step(gd_sim *sim, int mode, const float *actions, const uint8_t *mask,
+                              hipStream_t s) {
+    StepCtl c = sim->ctl;
+    c.mode = mode;
+    c.actions = (const float2 *)actions;
+    c.mask = mask;
+    TIMED(sim, s, GD_PHASE_STEP, launch_step(sim->args, c, sim->waves, sim->bins, s), "step launch");
+    if (sim->args.N > 0 && sim->args.A > 0)
+        TIMED(sim, s, GD_PHASE_LIDAR, launch_lidar_impl(sim->args, sim->max_agents, s), "lidar launch");
+    return GD_OK;
+}
+
+// graph mode: build once, then re-point the nodes at the current actions and outputs
+static gd_status graph_step(gd_sim *sim, const float *actions, hipStream_t s) {
+    sim->graph_args = sim->args;
+    sim->graph_ctl = sim->ctl;
+    sim->graph_ctl.mode = kModeStep;
+    sim->graph_ctl.actions = (const float2 *)actions;
+    sim->graph_ctl.mask = nullptr;
+    hipKernelNodeParams sp{}, lp{};
+    void *sargs[2], *largs[2];
+    if (!step_kernel_node(&sim->graph_args, &sim->graph_ctl, sim->waves, sim->bins, sp, sargs))
+        return fail(GD_E_STATE, "no step kernel for this launch shape");
+    const bool lidar = sim->args.N > 0 && sim->args.A > 0;
+    if (lidar && !lidar_kernel_node(&sim->graph_args, sim->max_agents, lp, largs))
+        return fail(GD_E_STATE, "no lidar kernel");
+    if (!sim->graph_exec) {
+        HIP_TRY(hipGraphCreate(&sim->graph, 0), "graph create");
+        HIP_TRY(hipGraphAddKernelNode(&sim->step_node, sim->graph, nullptr, 0, &sp), "graph step node");
+        if (lidar)
+            HIP_TRY(hipGraphAddKernelNode(&sim->lidar_node, sim->graph, &sim->step_node, 1, &lp),
+                    "graph lidar node");
+        HIP_TRY(hipGraphInstantiate(&sim->graph_exec, sim->graph, nullptr, nullptr, 0), "graph instantiate");
+    } else {
+        HIP_TRY(hipGraphExecKernelNodeSetParams(sim->graph_exec, sim->step_node, &sp), "graph step params");
+        if (lidar)
+            HIP_TRY(hipGraphExecKernelNodeSetParams(sim->graph_exec, sim->lidar_node, &lp),
+                    "graph lidar params");
+    }
+    TIMED(sim, s, GD_PHASE_STEP, hipGraphLaunch(sim->graph_exec, s), "graph launch");
+    return GD_OK;
 }
 
 extern "C" {
@@ -206,11 +284,8 @@ gd_status gd_workspace_size(const gd_config *cfg, const int32_t *h_agent_off,
     gd_status st = check_config(cfg, h_agent_off, h_road_off);
     if (st != GD_OK) return st;
     if (!bytes) return fail(GD_E_ARG, "bytes is NULL");
-    int waves, bins, chunk;
-    launch_shape(cfg, waves, bins, chunk);
     const int W = cfg->num_worlds;
-    Layout L = make_layout(W, h_agent_off[W], h_road_off[W], n_items_of(cfg, h_agent_off, chunk));
-    *bytes = L.total;
+    *bytes = make_layout(W, h_agent_off[W], h_road_off[W]).total;
     return GD_OK;
 }
 
@@ -234,13 +309,12 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
         return fail(GD_E_ARG, "road buffers are NULL");
     const long long S = partner_slots_of(cfg, h_agent_off);
     if (S > 0 && (!b->obs_partner || !b->partner_mask)) return fail(GD_E_ARG, "partner buffers are NULL");
-    if (cfg->top_k > 0 && A > 0 && (!b->obs_road || !b->road_idx)) return fail(GD_E_ARG, "road obs buffers are NULL");
-    if (cfg->lidar_rays > 0 && A > 0 && (!b->lidar || !b->lidar_hit)) return fail(GD_E_ARG, "lidar buffers are NULL");
+    if (cfg->top_k > 0 && A > 0 && (!b->obs_road || !b->road_idx))
+        return fail(GD_E_ARG, "road obs buffers are NULL");
+    if (cfg->lidar_rays > 0 && A > 0 && (!b->lidar || !b->lidar_hit))
+        return fail(GD_E_ARG, "lidar buffers are NULL");
     if (((uintptr_t)b->workspace) & 255) return fail(GD_E_ARG, "workspace must be 256-byte aligned");
-    int waves, bins, chunk;
-    launch_shape(cfg, waves, bins, chunk);
-    std::vector<ObsItem> items = make_items(cfg, h_agent_off, h_road_off, chunk);
-    Layout L = make_layout(W, A, R, (long long)items.size());
+    Layout L = make_layout(W, A, R);
     if (b->workspace_bytes < L.total)
         return fail(GD_E_SIZE, "workspace too small: %zu bytes, need %zu", b->workspace_bytes, L.total);
     int max_road = 0, max_agents = 0;
@@ -248,15 +322,22 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
         max_road = std::max(max_road, h_road_off[w + 1] - h_road_off[w]);
         max_agents = std::max(max_agents, h_agent_off[w + 1] - h_agent_off[w]);
     }
+    int waves = 0, bins = 0, road_cap = 0, cand_cap = 0;
+    if (!launch_shape(cfg, max_road, max_agents, waves, bins, road_cap, cand_cap))
+        return fail(GD_E_SIZE, "no launch shape fits the LDS (top_k %d, %d agents per world)",
+                    cfg->top_k, max_agents);
+    const std::vector<int> order = world_order(W, h_agent_off, h_road_off);
     hipStream_t s = (hipStream_t)stream;
     // device offsets must hold the host values
     {
         std::vector<int32_t> chk(W + 1);
-        HIP_TRY(hipMemcpyAsync(chk.data(), b->agent_off, sizeof(int32_t) * (W + 1), hipMemcpyDeviceToHost, s), "copy agent_off");
+        HIP_TRY(hipMemcpyAsync(chk.data(), b->agent_off, sizeof(int32_t) * (W + 1), hipMemcpyDeviceToHost, s),
+                "copy agent_off");
         HIP_TRY(hipStreamSynchronize(s), "sync");
         if (memcmp(chk.data(), h_agent_off, sizeof(int32_t) * (W + 1)))
             return fail(GD_E_ARG, "device agent_off differs from h_agent_off");
-        HIP_TRY(hipMemcpyAsync(chk.data(), b->road_off, sizeof(int32_t) * (W + 1), hipMemcpyDeviceToHost, s), "copy road_off");
+        HIP_TRY(hipMemcpyAsync(chk.data(), b->road_off, sizeof(int32_t) * (W + 1), hipMemcpyDeviceToHost, s),
+                "copy road_off");
         HIP_TRY(hipStreamSynchronize(s), "sync");
         if (memcmp(chk.data(), h_road_off, sizeof(int32_t) * (W + 1)))
             return fail(GD_E_ARG, "device road_off differs from h_road_off");
@@ -268,11 +349,9 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
     sim->lay = L;
     sim->waves = waves;
     sim->bins = bins;
-    sim->chunk = chunk;
     sim->max_road = max_road;
     sim->max_agents = max_agents;
     sim->slots = S;
-    sim->n_items = (int)items.size();
     char *ws = (char *)b->workspace;
     SimArgs &a = sim->args;
     a.W = W;
@@ -331,7 +410,10 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
     a.snap = (float4 *)(ws + L.snap);
     a.pbase = (long long *)(ws + L.pbase);
     a.err = (unsigned *)(ws + L.err);
-    sim->d_items = (ObsItem *)(ws + L.items);
+    sim->ctl.order = (const int *)(ws + L.order);
+    sim->ctl.road_cap = road_cap;
+    sim->ctl.agent_cap = std::max(max_agents, 1);
+    sim->ctl.cand_cap = cand_cap;
 
     std::vector<long long> pb(W);
     long long acc = 0;
@@ -342,14 +424,15 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
     }
     hipError_t e;
     if ((e = hipMemcpyAsync(a.pbase, pb.data(), sizeof(long long) * W, hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(sim->d_items, items.data(), sizeof(ObsItem) * items.size(), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync((void *)sim->ctl.order, order.data(), sizeof(int) * W, hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
         (e = hipMemsetAsync(a.err, 0, 256, s)) != hipSuccess) {
         delete sim;
         return hip_fail(e, "workspace init");
     }
     if (A > 0) {
-        hipLaunchKernelGGL(k_snapshot, dim3((unsigned)((A + 255) / 256)), dim3(256), 0, s, a.x, a.y, a.yaw,
-                           a.v, a.snap, (int)A);
+        hipLaunchKernelGGL(k_snapshot, dim3((unsigned)((A + 255) / 256)), dim3(256), 0, s, a.x, a.y,
+                           a.yaw, a.v, a.snap, (int)A);
         if ((e = hipGetLastError()) != hipSuccess) {
             delete sim;
             return hip_fail(e, "snapshot");
@@ -363,86 +446,34 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
         delete sim;
         return hip_fail(e, "grid build sync");
     }
-    *out = sim;
-    st = gd_reset(sim, nullptr, stream);
+    st = enqueue_step(sim, kModeReset, nullptr, nullptr, s);
     if (st != GD_OK) {
         delete sim;
-        *out = nullptr;
         return st;
     }
     if ((e = hipStreamSynchronize(s)) != hipSuccess) {
         delete sim;
-        *out = nullptr;
         return hip_fail(e, "reset sync");
     }
-    return GD_OK;
-}
-
-// ---- optional event pair around each kernel (gd_set_timing)
-static hipError_t t_begin(gd_sim *sim, hipStream_t s, size_t &idx) {
-    if (!sim->timing) return hipSuccess;
-    while (sim->events_used + 2 > sim->events.size()) {
-        hipEvent_t ev;
-        hipError_t e = hipEventCreate(&ev);
-        if (e != hipSuccess) return e;
-        sim->events.push_back(ev);
-    }
-    idx = sim->events_used;
-    sim->events_used += 2;
-    return hipEventRecord(sim->events[idx], s);
-}
-
-static hipError_t t_end(gd_sim *sim, hipStream_t s, size_t idx, int phase) {
-    if (!sim->timing) return hipSuccess;
-    sim->records.push_back({idx, phase});
-    return hipEventRecord(sim->events[idx + 1], s);
-}
-
-#define TIMED(sim, s, phase, launch_expr, what)                  \
-    do {                                                          \
-        size_t ti_ = 0;                                           \
-        hipError_t te_ = t_begin(sim, s, ti_);                    \
-        if (te_ != hipSuccess) return hip_fail(te_, "timing event"); \
-        hipError_t le_ = (launch_expr);                           \
-        if (le_ != hipSuccess) return hip_fail(le_, what);        \
-        te_ = t_end(sim, s, ti_, phase);                          \
-        if (te_ != hipSuccess) return hip_fail(te_, "timing event"); \
-    } while (0)
-
-static gd_status enqueue_obs(gd_sim *sim, hipStream_t s) {
-    if ((sim->args.K > 0 || sim->slots > 0) && sim->n_items > 0)
-        TIMED(sim, s, GD_PHASE_ROAD_OBS,
-              launch_road_obs_impl(sim->args, sim->d_items, sim->n_items, sim->waves, sim->bins,
-                                   sim->max_road, sim->max_agents, s),
-              "observation launch");
-    if (sim->args.N > 0 && sim->args.A > 0)
-        TIMED(sim, s, GD_PHASE_LIDAR, launch_lidar_impl(sim->args, sim->max_agents, s), "lidar launch");
+    *out = sim;
     return GD_OK;
 }
 
 gd_status gd_reset(gd_sim *sim, const uint8_t *world_mask, void *stream) {
     if (!sim) return fail(GD_E_ARG, "sim is NULL");
-    hipStream_t s = (hipStream_t)stream;
-    TIMED(sim, s, GD_PHASE_WORLD, launch_world_step(sim->args, kModeReset, nullptr, world_mask, s),
-          "reset launch");
-    return enqueue_obs(sim, s);
+    return enqueue_step(sim, kModeReset, nullptr, world_mask, (hipStream_t)stream);
 }
 
 gd_status gd_obs(gd_sim *sim, void *stream) {
     if (!sim) return fail(GD_E_ARG, "sim is NULL");
-    hipStream_t s = (hipStream_t)stream;
-    TIMED(sim, s, GD_PHASE_WORLD, launch_world_step(sim->args, kModeObs, nullptr, nullptr, s),
-          "obs launch");
-    return enqueue_obs(sim, s);
+    return enqueue_step(sim, kModeObs, nullptr, nullptr, (hipStream_t)stream);
 }
 
 gd_status gd_step(gd_sim *sim, const float *actions, void *stream) {
     if (!sim) return fail(GD_E_ARG, "sim is NULL");
     if (!actions && sim->args.A > 0) return fail(GD_E_ARG, "actions is NULL");
-    hipStream_t s = (hipStream_t)stream;
-    TIMED(sim, s, GD_PHASE_WORLD,
-          launch_world_step(sim->args, kModeStep, (const float2 *)actions, nullptr, s), "step launch");
-    return enqueue_obs(sim, s);
+    if (sim->cfg.flags & GD_USE_GRAPH) return graph_step(sim, actions, (hipStream_t)stream);
+    return enqueue_step(sim, kModeStep, actions, nullptr, (hipStream_t)stream);
 }
 
 gd_status gd_rollout_fwd(gd_sim *sim, const float *actions, int32_t T, int32_t ckpt_every,
@@ -479,7 +510,8 @@ gd_status gd_check(gd_sim *sim, void *stream) {
     if (!sim) return fail(GD_E_ARG, "sim is NULL");
     hipStream_t s = (hipStream_t)stream;
     unsigned word = 0;
-    HIP_TRY(hipMemcpyAsync(&word, sim->args.err, sizeof(unsigned), hipMemcpyDeviceToHost, s), "read error word");
+    HIP_TRY(hipMemcpyAsync(&word, sim->args.err, sizeof(unsigned), hipMemcpyDeviceToHost, s),
+            "read error word");
     HIP_TRY(hipStreamSynchronize(s), "sync");
     if (word) {
         HIP_TRY(hipMemsetAsync(sim->args.err, 0, sizeof(unsigned), s), "clear error word");
@@ -493,8 +525,10 @@ gd_status gd_set_obs_buffers(gd_sim *sim, const gd_buffers *b) {
     if (!sim || !b) return fail(GD_E_ARG, "NULL argument");
     SimArgs &a = sim->args;
     if (!b->obs_ego) return fail(GD_E_ARG, "buffer obs_ego is NULL");
-    if (sim->slots > 0 && (!b->obs_partner || !b->partner_mask)) return fail(GD_E_ARG, "partner buffers are NULL");
-    if (a.K > 0 && a.A > 0 && (!b->obs_road || !b->road_idx)) return fail(GD_E_ARG, "road obs buffers are NULL");
+    if (sim->slots > 0 && (!b->obs_partner || !b->partner_mask))
+        return fail(GD_E_ARG, "partner buffers are NULL");
+    if (a.K > 0 && a.A > 0 && (!b->obs_road || !b->road_idx))
+        return fail(GD_E_ARG, "road obs buffers are NULL");
     if (a.N > 0 && a.A > 0 && (!b->lidar || !b->lidar_hit)) return fail(GD_E_ARG, "lidar buffers are NULL");
     a.ego = b->obs_ego;
     a.partner = b->obs_partner;

@@ -62,27 +62,32 @@ struct SimArgs {
     unsigned *err;     // device error word
 };
 
-// Work item of the observation kernel: agents [a0, a1) of world w.
-struct ObsItem {
-    int w, a0, a1, pad;
-};
-
 enum StepMode { kModeStep = 0, kModeObs = 1, kModeReset = 2 };
+
+constexpr int kLdsBytes = 160 * 1024 - 1024;  // LDS of one gfx950 CU, less room for static LDS
+
+// Per-launch control block of the fused step kernel.
+struct StepCtl {
+    int mode;                  // StepMode
+    const float2 *actions;     // [A] (kModeStep)
+    const uint8_t *mask;       // [W] worlds to reset (kModeReset; NULL = all)
+    const int *order;          // [W] world of each workgroup (longest first), NULL = identity
+    int road_cap;              // road points staged in LDS per world (0 = read from global)
+    int agent_cap;             // agents per world held in LDS
+    int cand_cap;              // candidate list entries per wave
+};
 
 // Workspace layout (byte offsets, each 256-aligned).
 struct Layout {
-    size_t grid, cell_start, pt_xy, pt_aux, ecell_start, eseg, eseg_id, snap, pbase, err,
-        items, total;
+    size_t grid, cell_start, pt_xy, pt_aux, ecell_start, eseg, eseg_id, snap, pbase, err, order,
+        total;
 };
-Layout make_layout(int W, long long A, long long R, long long n_items);
+Layout make_layout(int W, long long A, long long R);
 
 // launchers (return hipError_t of the launch)
 hipError_t launch_build_grid(const SimArgs &a, float cell_size, hipStream_t s);
-hipError_t launch_world_step(const SimArgs &a, int mode, const float2 *actions,
-                             const uint8_t *mask, hipStream_t s);
-
-// LDS bytes the observation kernel needs for a given shape (0 = does not fit)
-size_t road_obs_lds_bytes(int waves, int bins, int K, int max_road);
+hipError_t launch_step(const SimArgs &a, const StepCtl &c, int waves, int bins, hipStream_t s);
+size_t step_lds_bytes(int waves, int NB, int K, int ccap, int road_cap, int agent_cap);
 
 // ---------------------------------------------------------------- device helpers
 

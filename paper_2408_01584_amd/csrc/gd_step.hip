@@ -1,15 +1,35 @@
-// Per-world part of the step: bicycle dynamics, agent/agent and agent/road-edge
-// collision, goal / reward / done, auto-reset, and the ego observation.
+// The batched step, fused into one kernel launch: one workgroup per world.
 //
-// One workgroup per world.  A world's agents (at most GD_MAX_AGENTS_PER_WORLD) are
-// staged in LDS so the all-pairs collision test and the partner features read them from
-// there; the road-edge test walks the world's edge-segment grid.
+//   phase 1  bicycle dynamics of the alive agents (App. B)
+//   phase 2  agent/agent oriented-box collision (all pairs of the world, spread over the
+//            workgroup) and agent/road-edge collision (one wave per agent over the edge
+//            segments of the grid cells under the box) -- Sec. 3.1, Sec. 3.2
+//   phase 3  goal, reward, done, world done; auto-reset from the snapshot (Sec. 3.2
+//            "Rewards", "Termination")
+//   phase 4  ego observation (thread per agent)
+//   phase 5  partner observation and road radius filter + top-K (wave per agent; Fig. 1,
+//            Sec. 3.2 "Sensor modalities")
+//
+// The world's agents and, when they fit, its cell-sorted road points live in LDS for the
+// whole step, so the state is read once and written once.  gd_reset and gd_obs run the
+// same kernel in other modes.
+//
+// Top-K without a sort, per agent:
+//   a. the grid rows that meet the disc are contiguous ranges of cell-sorted points; one
+//      lane computes each row's range;
+//   b. one scan: binary32 key d2 of every point in those ranges; points within the radius
+//      go to a per-wave candidate list (ballot compaction) and into a histogram of
+//      bin(d2) = floor(d2 * NB / R^2), a monotone function of d2;
+//   c. wave prefix scan of the histogram; the bin holding the K-th smallest key;
+//   d. the candidates of the bins up to that one are scattered bin by bin;
+//   e. rank = first slot of the bin + bin mates with smaller (d2, index): an exact order
+//      by (d2, index);
+//   f. the K slots are written in order as float4 rows (x', y', dir', type) + index.
+// A cut bin too large for the staging array is resolved element by element by a wave
+// min-reduction (exact, slow, for pathological point clusters only).
 #include "gd_internal.h"
 
 namespace gdk {
-
-constexpr int kStepThreads = 256;
-constexpr int kMaxA = GD_MAX_AGENTS_PER_WORLD;
 
 // ---- bicycle model (App. B): midpoint speed, slip angle with l_r = L/2, explicit Euler
 __device__ __forceinline__ void bicycle(float &x, float &y, float &yaw, float &v, float L,
@@ -31,14 +51,12 @@ __device__ __forceinline__ void bicycle(float &x, float &y, float &yaw, float &v
 __device__ __forceinline__ float sat_box_box(float dx, float dy, float ci, float si, float Li,
                                              float Wi, float cj, float sj, float Lj, float Wj) {
     float hLi = 0.5f * Li, hWi = 0.5f * Wi, hLj = 0.5f * Lj, hWj = 0.5f * Wj;
-    // axes of i
     float uu = fabsf(ci * cj + si * sj);   // |u_i . u_j|
     float uv = fabsf(-ci * sj + si * cj);  // |u_i . v_j|
     float vu = fabsf(-si * cj + ci * sj);  // |v_i . u_j|
     float vv = fabsf(si * sj + ci * cj);   // |v_i . v_j|
     float s1 = fabsf(dx * ci + dy * si) - hLi - (hLj * uu + hWj * uv);
     float s2 = fabsf(-dx * si + dy * ci) - hWi - (hLj * vu + hWj * vv);
-    // axes of j
     float s3 = fabsf(dx * cj + dy * sj) - hLj - (hLi * uu + hWi * vu);
     float s4 = fabsf(-dx * sj + dy * cj) - hWj - (hLi * uv + hWi * vv);
     return fmaxf(fmaxf(s1, s2), fmaxf(s3, s4));
@@ -64,32 +82,109 @@ __device__ __forceinline__ float sat_box_seg(float c, float s, float hL, float h
     return sep;
 }
 
-__global__ __launch_bounds__(kStepThreads) void k_world_step(SimArgs a, int mode,
-                                                            const float2 *__restrict__ actions,
-                                                            const uint8_t *__restrict__ mask) {
-    __shared__ float sx[kMaxA], sy[kMaxA], syaw[kMaxA], sv[kMaxA], sL[kMaxA], sW[kMaxA];
-    __shared__ float sc[kMaxA], ss[kMaxA];
-    __shared__ uint8_t sf[kMaxA], sf2[kMaxA];
-    __shared__ int s_any;
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
 
-    const int w = blockIdx.x;
+// points of grid row r that can lie within R of (px, py): [q0, q1) of the cell-sorted array
+__device__ __forceinline__ void row_span(const WorldGrid &g, const int *cst, int r, float px,
+                                         float py, float R, float marg, int &q0, int &q1) {
+    float ylo = g.oy + (float)r * g.cs;
+    float yhi = ylo + g.cs;
+    float dy = fmaxf(fmaxf(ylo - py, py - yhi), 0.0f) - marg;
+    dy = fmaxf(dy, 0.0f);
+    if (!(dy <= R)) {
+        q0 = q1 = 0;
+        return;
+    }
+    float hw = sqrtf(fmaxf(R * R - dy * dy, 0.0f)) + marg;
+    int c0 = cell_coord(px - hw, g.ox, g.inv_cs, g.nx);
+    int c1 = cell_coord(px + hw, g.ox, g.inv_cs, g.nx);
+    q0 = cst[r * g.nx + c0];
+    q1 = cst[r * g.nx + c1 + 1];
+}
+
+__device__ __forceinline__ int bin_of(float k, float bscale, int NB) {
+    int b = (int)(k * bscale);
+    return b < NB - 1 ? b : NB - 1;
+}
+
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        unsigned lo = __shfl_xor((unsigned)v, d, kWave);
+        unsigned hi = __shfl_xor((unsigned)(v >> 32), d, kWave);
+        unsigned long long o = ((unsigned long long)hi << 32) | lo;
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int lane_prefix(unsigned long long mask) {
+    return __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
+__host__ __device__ inline int stage_cap(int K) { return ((K + 64 + 63) / 64) * 64; }
+
+// per-wave LDS: histogram NB ints | candidate list ccap ints | staging scap ints | perm K ushorts
+__host__ __device__ inline size_t wave_lds_bytes(int NB, int K, int ccap) {
+    size_t b = (size_t)NB * 4 + (size_t)ccap * 4 + (size_t)stage_cap(K) * 4 + (size_t)K * 2;
+    return (b + 15) / 16 * 16;
+}
+
+constexpr int kAgentArrays = 10;  // x y yaw v L W cos sin flags coll
+
+template <int NB, bool STAGED>
+__global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int BPL = NB / kWave;  // bins per lane
+    const int w = c.order ? c.order[blockIdx.x] : (int)blockIdx.x;
     const int tid = threadIdx.x;
+    const int bs = blockDim.x;
+    const int nwaves = bs / kWave;
+    const int wid = tid / kWave;
+    const int lane = tid & (kWave - 1);
     const int a0 = a.agent_off[w];
     const int n = a.agent_off[w + 1] - a0;
-    int t = a.t[w];
-    bool do_reset = false;
-    bool keep_outcome = false;
+    const int r0 = a.road_off[w];
+    const int nr = a.road_off[w + 1] - r0;
+    const int K = a.K;
+    const int scap = stage_cap(K);
+    const int ccap = c.cand_cap;
+    const int S = a.P >= 0 ? a.P : (n > 0 ? n - 1 : 0);
+    const int mode = c.mode;
 
-    if (mode == kModeStep) {
-        // 1. dynamics of the alive agents
+    float2 *sroad = reinterpret_cast<float2 *>(smem);
+    float *sag = reinterpret_cast<float *>(smem + (STAGED ? (size_t)c.road_cap * 8 : 0));
+    const int ac = c.agent_cap;
+    float *sx = sag, *sy = sag + ac, *syaw = sag + 2 * ac, *sv = sag + 3 * ac;
+    float *sL = sag + 4 * ac, *sW = sag + 5 * ac, *sc = sag + 6 * ac, *ss = sag + 7 * ac;
+    int *sf = reinterpret_cast<int *>(sag + 8 * ac);
+    int *scoll = reinterpret_cast<int *>(sag + 9 * ac);
+    unsigned char *mine = reinterpret_cast<unsigned char *>(sag + kAgentArrays * ac) +
+                          (size_t)wid * wave_lds_bytes(NB, K, ccap);
+    int *hist = reinterpret_cast<int *>(mine);
+    int *cand = hist + NB;
+    int *stage = cand + ccap;
+    unsigned short *perm = reinterpret_cast<unsigned short *>(stage + scap);
+
+    // phase 0: the world's road points into LDS (consumed in phase 5)
+    if (STAGED && K > 0)
+        for (int k = tid; k < nr; k += bs) sroad[k] = a.pt_xy[r0 + k];
+
+    // phase 1: agents into LDS, dynamics of the alive ones
+    int t = a.t[w];
+    {
         bool nonfinite = false;
-        for (int i = tid; i < n; i += kStepThreads) {
+        for (int i = tid; i < n; i += bs) {
             const int gi = a0 + i;
-            uint8_t f = a.fl[gi];
+            const int f = a.fl[gi];
             float x = a.x[gi], y = a.y[gi], yaw = a.yaw[gi], v = a.v[gi];
-            float L = a.len[gi];
-            if (f & GD_FLAG_ALIVE) {
-                float2 act = actions[gi];
+            const float L = a.len[gi];
+            if (mode == kModeStep && (f & GD_FLAG_ALIVE)) {
+                const float2 act = c.actions[gi];
                 if (!(isfinite(act.x) && isfinite(act.y))) nonfinite = true;
                 bicycle(x, y, yaw, v, L, act.x, act.y, a.dt, a.vmax);
                 a.x[gi] = x;
@@ -108,41 +203,37 @@ __global__ __launch_bounds__(kStepThreads) void k_world_step(SimArgs a, int mode
             sc[i] = cs;
             ss[i] = sn;
             sf[i] = f;
+            scoll[i] = 0;
         }
         if (nonfinite && (a.flags & GD_CHECK_FINITE)) atomicOr(a.err, 1u);
-        if (tid == 0) s_any = 0;
-        __syncthreads();
+    }
+    __syncthreads();
 
-        // 2-4. collisions on the new state, then goal / reward / done
-        const WorldGrid g = a.grid[w];
-        const int r0 = a.road_off[w];
-        const int *ecs = a.ecell_start + (size_t)w * kCellStride;
-        const float4 *es = a.eseg + r0;
-        const bool last = t + 1 >= a.T_ep;
-        int any = 0;
-        for (int i = tid; i < n; i += kStepThreads) {
-            const int gi = a0 + i;
-            const uint8_t f = sf[i];
-            uint8_t out = 0;
-            float r = 0.0f;
-            bool done = true;
-            if (f & GD_FLAG_ALIVE) {
+    bool do_reset = false, keep_outcome = false;
+    if (mode == kModeStep) {
+        // phase 2a: all agent pairs of the world over the whole workgroup
+        const int npairs = n * n;
+        for (int e = tid; e < npairs; e += bs) {
+            const int i = e / n;
+            const int j = e - i * n;
+            if (i == j || !(sf[i] & GD_FLAG_ALIVE) || !(sf[j] & GD_FLAG_ALIVE)) continue;
+            const float dx = sx[j] - sx[i], dy = sy[j] - sy[i];
+            const float rr = 0.5f * (sqrtf(sL[i] * sL[i] + sW[i] * sW[i]) +
+                                     sqrtf(sL[j] * sL[j] + sW[j] * sW[j])) + 1e-3f;
+            if (dx * dx + dy * dy > rr * rr) continue;
+            if (sat_box_box(dx, dy, sc[i], ss[i], sL[i], sW[i], sc[j], ss[j], sL[j], sW[j]) < 0.0f)
+                atomicOr(&scoll[i], (int)GD_FLAG_COLL_AGENT);
+        }
+        // phase 2b: road edges, one wave per agent, lanes over the segments of the cells
+        // under the box (segments are keyed by their first point: widen by max_seg)
+        {
+            const WorldGrid g = a.grid[w];
+            const int *ecs = a.ecell_start + (size_t)w * kCellStride;
+            const float4 *es = a.eseg + r0;
+            for (int i = wid; i < n; i += nwaves) {
+                if (!(sf[i] & GD_FLAG_ALIVE)) continue;
                 const float xi = sx[i], yi = sy[i], ci = sc[i], si = ss[i];
-                const float Li = sL[i], Wi = sW[i];
-                const float ri = 0.5f * sqrtf(Li * Li + Wi * Wi);
-                for (int j = 0; j < n; j++) {
-                    if (j == i || !(sf[j] & GD_FLAG_ALIVE)) continue;
-                    float dx = sx[j] - xi, dy = sy[j] - yi;
-                    float rj = 0.5f * sqrtf(sL[j] * sL[j] + sW[j] * sW[j]);
-                    float rr = ri + rj + 1e-3f;
-                    if (dx * dx + dy * dy > rr * rr) continue;
-                    if (sat_box_box(dx, dy, ci, si, Li, Wi, sc[j], ss[j], sL[j], sW[j]) < 0.0f) {
-                        out |= GD_FLAG_COLL_AGENT;
-                        break;
-                    }
-                }
-                // road edges: segments keyed by their first point, so widen by max_seg
-                const float hL = 0.5f * Li, hW = 0.5f * Wi;
+                const float hL = 0.5f * sL[i], hW = 0.5f * sW[i];
                 const float ex = fabsf(ci) * hL + fabsf(si) * hW;
                 const float ey = fabsf(si) * hL + fabsf(ci) * hW;
                 const float m = g.max_seg + 1e-3f;
@@ -152,23 +243,37 @@ __global__ __launch_bounds__(kStepThreads) void k_world_step(SimArgs a, int mode
                 const int cy1 = cell_coord(yi + ey + m, g.oy, g.inv_cs, g.ny);
                 bool hit = false;
                 for (int cy = cy0; cy <= cy1 && !hit; cy++) {
-                    int q0 = ecs[cy * g.nx + cx0], q1 = ecs[cy * g.nx + cx1 + 1];
-                    for (int q = q0; q < q1; q++) {
-                        float4 e = es[q];
-                        float x0 = e.x - xi, y0 = e.y - yi, x1 = e.z - xi, y1 = e.w - yi;
-                        // cheap reject on the axis-aligned boxes
-                        if (fminf(x0, x1) > ex || fmaxf(x0, x1) < -ex || fminf(y0, y1) > ey ||
-                            fmaxf(y0, y1) < -ey)
-                            continue;
-                        if (sat_box_seg(ci, si, hL, hW, x0, y0, x1, y1) < 0.0f) {
-                            hit = true;
-                            break;
+                    const int q0 = ecs[cy * g.nx + cx0], q1 = ecs[cy * g.nx + cx1 + 1];
+                    for (int base = q0; base < q1 && !hit; base += kWave) {
+                        const int q = base + lane;
+                        bool h = false;
+                        if (q < q1) {
+                            const float4 e = es[q];
+                            const float x0 = e.x - xi, y0 = e.y - yi, x1 = e.z - xi, y1 = e.w - yi;
+                            if (!(fminf(x0, x1) > ex || fmaxf(x0, x1) < -ex || fminf(y0, y1) > ey ||
+                                  fmaxf(y0, y1) < -ey))
+                                h = sat_box_seg(ci, si, hL, hW, x0, y0, x1, y1) < 0.0f;
                         }
+                        hit = __ballot(h) != 0ull;
                     }
                 }
-                if (hit) out |= GD_FLAG_COLL_EDGE;
-                const bool goal = key32(xi, yi, a.gx[gi], a.gy[gi]) <= a.goal_r2;
-                const bool coll = (out & (GD_FLAG_COLL_AGENT | GD_FLAG_COLL_EDGE)) != 0;
+                if (hit && lane == 0) atomicOr(&scoll[i], (int)GD_FLAG_COLL_EDGE);
+            }
+        }
+        __syncthreads();
+        // phase 3: goal, reward, done
+        const bool last = t + 1 >= a.T_ep;
+        int any = 0;
+        for (int i = tid; i < n; i += bs) {
+            const int gi = a0 + i;
+            const int f = sf[i];
+            int out = 0;
+            float r = 0.0f;
+            bool done = true;
+            if (f & GD_FLAG_ALIVE) {
+                out = scoll[i];
+                const bool goal = key32(sx[i], sy[i], a.gx[gi], a.gy[gi]) <= a.goal_r2;
+                const bool coll = out != 0;
                 if (goal) out |= GD_FLAG_GOAL;
                 r = (goal ? 1.0f : 0.0f) - (coll ? a.penalty : 0.0f);
                 done = goal || ((a.flags & GD_TERMINATE_ON_COLLISION) && coll) || last;
@@ -179,42 +284,48 @@ __global__ __launch_bounds__(kStepThreads) void k_world_step(SimArgs a, int mode
                 }
             }
             if (done) out |= GD_FLAG_DONE;
-            sf2[i] = out;
+            scoll[i] = out;  // the transition's flags
             a.reward[gi] = r;
         }
-        if (any) s_any = 1;  // benign race: every writer stores 1
-        __syncthreads();
-        const bool wdone = !s_any || last;
+        any = __syncthreads_or(any);
+        const bool wdone = !any || last;
         if (tid == 0) a.world_done[w] = wdone ? 1 : 0;
         if (wdone && (a.flags & GD_AUTO_RESET)) {
             do_reset = true;
             keep_outcome = true;
         } else {
             t = t + 1;
-            for (int i = tid; i < n; i += kStepThreads) {
-                sf[i] = sf2[i];
-                a.fl[a0 + i] = sf2[i];
+            for (int i = tid; i < n; i += bs) {
+                sf[i] = scoll[i];
+                a.fl[a0 + i] = (uint8_t)scoll[i];
             }
         }
     } else if (mode == kModeReset) {
-        do_reset = (mask == nullptr) || (mask[w] != 0);
-        for (int i = tid; i < n; i += kStepThreads) sf2[i] = 0;
+        do_reset = (c.mask == nullptr) || (c.mask[w] != 0);
     }
 
     if (do_reset) {
-        for (int i = tid; i < n; i += kStepThreads) {
+        for (int i = tid; i < n; i += bs) {
             const int gi = a0 + i;
-            float4 s0 = a.snap[gi];
+            const float4 s0 = a.snap[gi];
             a.x[gi] = s0.x;
             a.y[gi] = s0.y;
             a.yaw[gi] = s0.z;
             a.v[gi] = s0.w;
-            uint8_t keep = keep_outcome ? (uint8_t)(sf2[i] & (GD_FLAG_COLL_AGENT | GD_FLAG_COLL_EDGE |
-                                                              GD_FLAG_GOAL | GD_FLAG_DONE))
-                                        : (uint8_t)0;
-            uint8_t f = keep | GD_FLAG_ALIVE | GD_FLAG_VISIBLE;
-            a.fl[gi] = f;
+            sx[i] = s0.x;
+            sy[i] = s0.y;
+            syaw[i] = s0.z;
+            sv[i] = s0.w;
+            float sn, cs;
+            sincosf(s0.z, &sn, &cs);
+            sc[i] = cs;
+            ss[i] = sn;
+            const int keep = keep_outcome ? (scoll[i] & (GD_FLAG_COLL_AGENT | GD_FLAG_COLL_EDGE |
+                                                         GD_FLAG_GOAL | GD_FLAG_DONE))
+                                          : 0;
+            const int f = keep | GD_FLAG_ALIVE | GD_FLAG_VISIBLE;
             sf[i] = f;
+            a.fl[gi] = (uint8_t)f;
             if (mode == kModeReset) a.reward[gi] = 0.0f;
         }
         t = 0;
@@ -223,33 +334,14 @@ __global__ __launch_bounds__(kStepThreads) void k_world_step(SimArgs a, int mode
     if (tid == 0) a.t[w] = t;
     __syncthreads();
 
-    // ---- ego observation of the resulting state
-    if (mode != kModeStep || do_reset) {
-        // state in LDS may be stale (obs-only, reset)
-        for (int i = tid; i < n; i += kStepThreads) {
-            const int gi = a0 + i;
-            float yaw = a.yaw[gi];
-            sx[i] = a.x[gi];
-            sy[i] = a.y[gi];
-            syaw[i] = yaw;
-            sv[i] = a.v[gi];
-            sL[i] = a.len[gi];
-            sW[i] = a.wid[gi];
-            float sn, cs;
-            sincosf(yaw, &sn, &cs);
-            sc[i] = cs;
-            ss[i] = sn;
-            if (!do_reset) sf[i] = a.fl[gi];  // obs-only, or a reset call that skips this world
-        }
-        __syncthreads();
-    }
+    // phase 4: ego observation
     const bool fresh = (t == 0);
-    for (int i = tid; i < n; i += kStepThreads) {
+    for (int i = tid; i < n; i += bs) {
         const int gi = a0 + i;
-        const uint8_t f = sf[i];
+        const int f = sf[i];
         float4 e0 = make_float4(0.f, 0.f, 0.f, 0.f), e1 = e0;
         if (f & GD_FLAG_VISIBLE) {
-            float gdx = a.gx[gi] - sx[i], gdy = a.gy[gi] - sy[i];
+            const float gdx = a.gx[gi] - sx[i], gdy = a.gy[gi] - sy[i];
             e0 = make_float4(sv[i], sL[i], sW[i], sc[i] * gdx + ss[i] * gdy);
             e1 = make_float4(-ss[i] * gdx + sc[i] * gdy,
                              (!fresh && (f & GD_FLAG_COLL_AGENT)) ? 1.0f : 0.0f,
@@ -259,13 +351,316 @@ __global__ __launch_bounds__(kStepThreads) void k_world_step(SimArgs a, int mode
         eo[0] = e0;
         eo[1] = e1;
     }
+
+    // phase 5: partners and road top-K, one wave per agent
+    const WorldGrid g = a.grid[w];
+    const float2 *rxy = STAGED ? sroad : (a.pt_xy + r0);
+    const float2 *aux = a.pt_aux + r0;
+    const int *cst = a.cell_start + (size_t)w * kCellStride;
+    const float R = a.R_obs, R2 = a.R2_obs;
+    const float bscale = (float)NB / R2;
+    const float marg = 1e-3f * g.cs + 1e-3f;
+
+    for (int l = wid; l < n; l += nwaves) {
+        const int ai = a0 + l;
+        const bool vis = (sf[l] & GD_FLAG_VISIBLE) != 0;
+        const float px = sx[l], py = sy[l], yaw = syaw[l], csy = sc[l], sny = ss[l];
+
+        // ---- partners: lane = slot; slot s holds the s-th other agent in index order
+        if (S > 0) {
+            const long long base = a.P >= 0 ? (long long)ai * a.P : a.pbase[w] + (long long)l * S;
+            for (int s = lane; s < S; s += kWave) {
+                const int j = s < l ? s : s + 1;
+                float f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f, f4 = 0.f, f5 = 0.f;
+                uint8_t m = 0;
+                if (vis && j < n && (sf[j] & GD_FLAG_VISIBLE) && key32(px, py, sx[j], sy[j]) <= R2) {
+                    const float dx = sx[j] - px, dy = sy[j] - py;
+                    f0 = csy * dx + sny * dy;
+                    f1 = -sny * dx + csy * dy;
+                    f2 = wrap_pi(syaw[j] - yaw);
+                    f3 = sv[j];
+                    f4 = sL[j];
+                    f5 = sW[j];
+                    m = 1;
+                }
+                float2 *po = reinterpret_cast<float2 *>(a.partner + (size_t)(base + s) * 6);
+                po[0] = make_float2(f0, f1);
+                po[1] = make_float2(f2, f3);
+                po[2] = make_float2(f4, f5);
+                a.pmask[base + s] = m;
+            }
+        }
+        if (K == 0) continue;
+
+        float4 *out = reinterpret_cast<float4 *>(a.road + (size_t)ai * K * 4);
+        int *oidx = a.road_idx + (size_t)ai * K;
+        if (!vis) {
+            for (int s = lane; s < K; s += kWave) {
+                out[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+                oidx[s] = -1;
+            }
+            continue;
+        }
+        for (int b = lane; b < NB; b += kWave) hist[b] = 0;
+        // a. candidate rows, one per lane (at most 64 rows per world)
+        const int rlo = cell_coord(py - R, g.oy, g.inv_cs, g.ny);
+        const int rhi = cell_coord(py + R, g.oy, g.inv_cs, g.ny);
+        const int nrows = rhi - rlo + 1;
+        int sq0 = 0, sq1 = 0;
+        if (lane < nrows) row_span(g, cst, rlo + lane, px, py, R, marg, sq0, sq1);
+        wave_sync();
+
+        // b. one scan: candidate list + histogram of bin(d2)
+        int ncand = 0;
+        for (int rr = 0; rr < nrows; rr++) {
+            const int q0 = __builtin_amdgcn_readlane(sq0, rr);
+            const int q1 = __builtin_amdgcn_readlane(sq1, rr);
+            for (int base = q0; base < q1; base += kWave) {
+                const int q = base + lane;
+                bool in = false;
+                if (q < q1) {
+                    const float2 p = rxy[q];
+                    const float k = key32(px, py, p.x, p.y);
+                    if (k <= R2) {
+                        in = true;
+                        atomicAdd(&hist[bin_of(k, bscale, NB)], 1);
+                    }
+                }
+                const unsigned long long bal = __ballot(in);
+                const int pos = ncand + lane_prefix(bal);
+                if (in && pos < ccap) cand[pos] = q;
+                ncand += __popcll(bal);
+            }
+        }
+        wave_sync();
+
+        // c. prefix scan: hist[b] <- first slot of bin b
+        int cnt[BPL];
+        int run = 0;
+#pragma unroll
+        for (int j = 0; j < BPL; j++) {
+            cnt[j] = hist[lane * BPL + j];
+            run += cnt[j];
+        }
+        int inc = run;
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int o = __shfl_up(inc, d, kWave);
+            if (lane >= d) inc += o;
+        }
+        const int total = __shfl(inc, kWave - 1, kWave);
+        {
+            int st = inc - run;
+#pragma unroll
+            for (int j = 0; j < BPL; j++) {
+                hist[lane * BPL + j] = st;
+                st += cnt[j];
+            }
+        }
+        const int nsel = total < K ? total : K;
+        int bstar = NB - 1;
+        int need = total;
+        if (total > K) {
+            int st = inc - run, mine_b = -1, mine_end = 0;
+#pragma unroll
+            for (int j = 0; j < BPL; j++) {
+                if (st < K && K <= st + cnt[j]) {
+                    mine_b = lane * BPL + j;
+                    mine_end = st + cnt[j];
+                }
+                st += cnt[j];
+            }
+            const unsigned long long bal = __ballot(mine_b >= 0);
+            const int src = __ffsll((long long)bal) - 1;
+            bstar = __shfl(mine_b, src, kWave);
+            need = __shfl(mine_end, src, kWave);
+        }
+        wave_sync();
+        const int cut_start = hist[bstar];
+        const bool overflow = need > scap;
+
+        // d. scatter the candidates of bins <= bstar, bin by bin (hist[b] becomes the end
+        //    of bin b, i.e. the start of bin b + 1, for every staged bin)
+        if (total <= ccap) {
+            for (int ci = lane; ci < total; ci += kWave) {
+                const int q = cand[ci];
+                const float2 p = rxy[q];
+                const float k = key32(px, py, p.x, p.y);
+                const int b = bin_of(k, bscale, NB);
+                if (b < bstar || (b == bstar && !overflow)) stage[atomicAdd(&hist[b], 1)] = q;
+            }
+        } else {
+            for (int rr = 0; rr < nrows; rr++) {
+                const int q0 = __builtin_amdgcn_readlane(sq0, rr);
+                const int q1 = __builtin_amdgcn_readlane(sq1, rr);
+                for (int base = q0; base < q1; base += kWave) {
+                    const int q = base + lane;
+                    if (q < q1) {
+                        const float2 p = rxy[q];
+                        const float k = key32(px, py, p.x, p.y);
+                        if (k <= R2) {
+                            const int b = bin_of(k, bscale, NB);
+                            if (b < bstar || (b == bstar && !overflow)) stage[atomicAdd(&hist[b], 1)] = q;
+                        }
+                    }
+                }
+            }
+        }
+        wave_sync();
+
+        // e. rank inside each bin by (d2, world-local index)
+        const int nstaged = overflow ? cut_start : need;
+        for (int p = lane; p < nstaged; p += kWave) {
+            const int q = stage[p];
+            const float2 pp = rxy[q];
+            const unsigned kb = __float_as_uint(key32(px, py, pp.x, pp.y));
+            const int b = bin_of(__uint_as_float(kb), bscale, NB);
+            const int lo = b > 0 ? hist[b - 1] : 0;
+            const int hi = hist[b];
+            int rank = 0;
+            int my_idx = -1;
+            for (int m = lo; m < hi; m++) {
+                const int qo = stage[m];
+                const float2 po = rxy[qo];
+                const unsigned ko = __float_as_uint(key32(px, py, po.x, po.y));
+                if (ko < kb) {
+                    rank++;
+                } else if (ko == kb && m != p) {
+                    if (my_idx < 0) my_idx = __float_as_int(aux[q].y) & 0xffffff;
+                    rank += (__float_as_int(aux[qo].y) & 0xffffff) < my_idx;
+                }
+            }
+            const int fin = lo + rank;
+            if (fin < K) perm[fin] = (unsigned short)p;
+        }
+
+        if (overflow) {
+            // the cut bin is too large to stage: take its members one at a time
+            unsigned long long prev = 0ull;
+            bool first = true;
+            for (int s = cut_start; s < K; s++) {
+                unsigned long long best = ~0ull;
+                for (int rr = 0; rr < nrows; rr++) {
+                    const int q0 = __builtin_amdgcn_readlane(sq0, rr);
+                    const int q1 = __builtin_amdgcn_readlane(sq1, rr);
+                    for (int base = q0; base < q1; base += kWave) {
+                        const int q = base + lane;
+                        if (q < q1) {
+                            const float2 p = rxy[q];
+                            const float k = key32(px, py, p.x, p.y);
+                            if (k <= R2 && bin_of(k, bscale, NB) == bstar) {
+                                const unsigned idx = (unsigned)(__float_as_int(aux[q].y) & 0xffffff);
+                                const unsigned long long key =
+                                    ((unsigned long long)__float_as_uint(k) << 32) | idx;
+                                if ((first || key > prev) && key < best) best = key;
+                            }
+                        }
+                    }
+                }
+                best = wave_min_u64(best);
+                prev = best;
+                first = false;
+                if (lane == 0) {
+                    const int idx = (int)(best & 0xffffffu);
+                    const float dx = a.rx[r0 + idx] - px, dy = a.ry[r0 + idx] - py;
+                    out[s] = make_float4(csy * dx + sny * dy, -sny * dx + csy * dy,
+                                         wrap_pi(a.rdir[r0 + idx] - yaw),
+                                         (float)(a.rmeta[r0 + idx] & 0xff));
+                    oidx[s] = idx;
+                }
+            }
+        }
+        wave_sync();
+
+        // f. the K slots in order
+        const int direct_end = overflow ? cut_start : nsel;
+        for (int s = lane; s < K; s += kWave) {
+            if (s < direct_end) {
+                const int q = stage[perm[s]];
+                const float2 p = rxy[q];
+                const float2 x2 = aux[q];
+                const int bits = __float_as_int(x2.y);
+                const float dx = p.x - px, dy = p.y - py;
+                out[s] = make_float4(csy * dx + sny * dy, -sny * dx + csy * dy, wrap_pi(x2.x - yaw),
+                                     (float)((unsigned)bits >> 24));
+                oidx[s] = bits & 0xffffff;
+            } else if (s >= nsel) {
+                out[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+                oidx[s] = -1;
+            }
+        }
+        wave_sync();
+    }
 }
 
-hipError_t launch_world_step(const SimArgs &a, int mode, const float2 *actions,
-                             const uint8_t *mask, hipStream_t s) {
-    if (a.W <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_world_step, dim3(a.W), dim3(kStepThreads), 0, s, a, mode, actions, mask);
+size_t step_lds_bytes(int waves, int NB, int K, int ccap, int road_cap, int agent_cap) {
+    return (size_t)road_cap * 8 + (size_t)agent_cap * 4 * kAgentArrays +
+           (size_t)waves * wave_lds_bytes(NB, K, ccap);
+}
+
+// raise the kernel's dynamic-LDS limit to what this launch needs (once per size increase)
+template <int NB, bool STAGED>
+static hipError_t prepare(size_t lds) {
+    static size_t allowed = 0;  // per instantiation
+    if (lds > allowed) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_step<NB, STAGED>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        allowed = lds;
+    }
+    return hipSuccess;
+}
+
+template <int NB, bool STAGED>
+static hipError_t launch_one(const SimArgs &a, const StepCtl &c, int waves, hipStream_t st) {
+    const size_t lds = step_lds_bytes(waves, NB, a.K, c.cand_cap, c.road_cap, c.agent_cap);
+    hipError_t e = prepare<NB, STAGED>(lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_step<NB, STAGED>), dim3(a.W), dim3(waves * kWave), lds, st, a, c);
     return hipGetLastError();
+}
+
+template <int NB, bool STAGED>
+static bool node_one(const SimArgs *a, const StepCtl *c, int waves, hipKernelNodeParams &p,
+                     void **args) {
+    const size_t lds = step_lds_bytes(waves, NB, a->K, c->cand_cap, c->road_cap, c->agent_cap);
+    if (prepare<NB, STAGED>(lds) != hipSuccess) return false;
+    p.func = (void *)k_step<NB, STAGED>;
+    p.gridDim = dim3(a->W);
+    p.blockDim = dim3(waves * kWave);
+    p.sharedMemBytes = (unsigned)lds;
+    args[0] = (void *)a;
+    args[1] = (void *)c;
+    p.kernelParams = args;
+    p.extra = nullptr;
+    return true;
+}
+
+// kernel node of the fused step for graph mode (same kernel and shape as launch_step)
+bool step_kernel_node(const SimArgs *a, const StepCtl *c, int waves, int bins,
+                      hipKernelNodeParams &p, void **args) {
+    const bool staged = c->road_cap != 0;
+    switch (bins) {
+        case 64: return staged ? node_one<64, true>(a, c, waves, p, args) : node_one<64, false>(a, c, waves, p, args);
+        case 128: return staged ? node_one<128, true>(a, c, waves, p, args) : node_one<128, false>(a, c, waves, p, args);
+        case 512: return staged ? node_one<512, true>(a, c, waves, p, args) : node_one<512, false>(a, c, waves, p, args);
+        default: return staged ? node_one<256, true>(a, c, waves, p, args) : node_one<256, false>(a, c, waves, p, args);
+    }
+}
+
+template <int NB>
+static hipError_t launch_nb(const SimArgs &a, const StepCtl &c, int waves, hipStream_t st) {
+    return c.road_cap ? launch_one<NB, true>(a, c, waves, st) : launch_one<NB, false>(a, c, waves, st);
+}
+
+hipError_t launch_step(const SimArgs &a, const StepCtl &c, int waves, int bins, hipStream_t st) {
+    if (a.W <= 0) return hipSuccess;
+    switch (bins) {
+        case 64: return launch_nb<64>(a, c, waves, st);
+        case 128: return launch_nb<128>(a, c, waves, st);
+        case 512: return launch_nb<512>(a, c, waves, st);
+        default: return launch_nb<256>(a, c, waves, st);
+    }
 }
 
 }  // namespace gdk

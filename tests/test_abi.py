@@ -49,7 +49,7 @@ def test_struct_layout_matches_header(G):
 #include "gd.h"
 int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\n", sizeof(gd_config), offsetof(gd_config, cell_size),
-         offsetof(gd_config, obs_chunk), sizeof(gd_buffers), offsetof(gd_buffers, t),
+         offsetof(gd_config, obs_cands), sizeof(gd_buffers), offsetof(gd_buffers, t),
          offsetof(gd_buffers, workspace_bytes));
   return 0;
 }'''
@@ -59,7 +59,7 @@ int main(void) {
         exe = os.path.join(d, "l")
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), "-o", exe, src])
         vals = [int(v) for v in subprocess.check_output([exe], text=True).split()]
-    want = [C.sizeof(G.gd_config), G.gd_config.cell_size.offset, G.gd_config.obs_chunk.offset,
+    want = [C.sizeof(G.gd_config), G.gd_config.cell_size.offset, G.gd_config.obs_cands.offset,
             C.sizeof(G.gd_buffers), G.gd_buffers.t.offset, G.gd_buffers.workspace_bytes.offset]
     assert vals == want
 
