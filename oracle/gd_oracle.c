@@ -256,6 +256,20 @@ double or_ray_segment(double ox, double oy, double dx, double dy, double x0, dou
     return -1.0;
 }
 
+/* 1 when the ray passes within OR_BAND of an end of the segment inside the range, or
+   runs along it: a hit that a perturbation of that size can create or remove */
+static int ray_segment_grazes(double ox, double oy, double dx, double dy, double x0, double y0,
+                              double x1, double y1, double tmax) {
+    double ends[2][2] = {{x0, y0}, {x1, y1}};
+    for (int k = 0; k < 2; k++) {
+        double wx = ends[k][0] - ox, wy = ends[k][1] - oy;
+        double along = wx * dx + wy * dy;
+        double perp = fabs(wx * dy - wy * dx);
+        if (along > -OR_BAND && along <= tmax + OR_BAND && perp < OR_BAND) return 1;
+    }
+    return 0;
+}
+
 static void box_corners(double cx, double cy, double yaw, double L, double W, double out[4][2]) {
     double c = cos(yaw), s = sin(yaw), hl = 0.5 * L, hw = 0.5 * W;
     double lx[4] = {hl, hl, -hl, -hl}, ly[4] = {hw, -hw, -hw, hw};
@@ -363,8 +377,11 @@ static void obs_world(const or_batch *b, const or_config *c, int w, const or_out
             double dx = cos(ang), dy = sin(ang);
             double best = c->lidar_range, second = INFINITY;
             int hit = 0;
+            int graze = 0;
             for (int e = r0; e < r1 - 1; e++) {
                 if (!is_edge_segment(b->rmeta, e)) continue;
+                graze |= ray_segment_grazes(px, py, dx, dy, b->rx[e], b->ry[e], b->rx[e + 1],
+                                            b->ry[e + 1], c->lidar_range);
                 double tt = or_ray_segment(px, py, dx, dy, b->rx[e], b->ry[e], b->rx[e + 1],
                                            b->ry[e + 1], c->lidar_range);
                 if (tt > 0.0) {
@@ -377,6 +394,9 @@ static void obs_world(const or_batch *b, const or_config *c, int w, const or_out
                 double cr[4][2];
                 box_corners(b->x[j], b->y[j], b->yaw[j], b->len[j], b->wid[j], cr);
                 for (int q = 0; q < 4; q++) {
+                    graze |= ray_segment_grazes(px, py, dx, dy, cr[q][0], cr[q][1],
+                                                cr[(q + 1) % 4][0], cr[(q + 1) % 4][1],
+                                                c->lidar_range);
                     double tt = or_ray_segment(px, py, dx, dy, cr[q][0], cr[q][1],
                                                cr[(q + 1) % 4][0], cr[(q + 1) % 4][1],
                                                c->lidar_range);
@@ -388,7 +408,7 @@ static void obs_world(const or_batch *b, const or_config *c, int w, const or_out
             }
             o->lidar[(int64_t)i * N + k] = best;
             o->lidar_hit[(int64_t)i * N + k] = hit;
-            if (o->band && (second - best < OR_BAND || fabs(best - c->lidar_range) < OR_BAND))
+            if (o->band && (second - best < OR_BAND || fabs(best - c->lidar_range) < OR_BAND || graze))
                 o->band[i] |= 16;
         }
     }

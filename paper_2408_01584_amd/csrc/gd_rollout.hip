@@ -1,16 +1,325 @@
-// Differentiable rollout kernels (forward with checkpoints, backward by recomputation).
+// Differentiable rollout: forward with checkpoints and backward by recomputation.
+//
+// Forward: one thread per agent runs T bicycle steps (App. B) and after each step the
+// smooth reward  r = -|g'| - softplus(s),  g' = R(-yaw)(g - p),  s = signed distance (in
+// the ego frame, positive on the right of the segment direction, i.e. off-road) to the
+// nearest road-edge segment within the observation radius (s = -R when there is none).
+// The reward is an instance of the configurable agent/road-distance rewards of Sec. 3.2
+// "Rewards".  The state before every ckpt_every-th step is saved.
+//
+// Backward: per segment of ckpt_every steps, last segment first, the forward is recomputed
+// from its checkpoint into LDS (states and nearest-segment choices), then the adjoint of
+// (x, y, yaw, v) is carried backwards through the reward and the dynamics, producing
+// dJ/d(accel, steer) for every step.  Segment choice, side and clip activity are held
+// constant; the result does not depend on ckpt_every.
 #include "gd_internal.h"
 
 namespace gdk {
 
-hipError_t launch_rollout_fwd_impl(const SimArgs &, const float2 *, int, int, float *, float *,
-                                   hipStream_t) {
-    return hipErrorNotSupported;
+constexpr int kRollThreads = 64;
+constexpr int kMaxCkpt = 32;
+
+struct EdgeChoice {
+    int q;          // cell-sorted position of the segment in the world's edge arrays, -1 = none
+    float side;     // +1 off-road (right of the segment direction), -1 on-road
+};
+
+// nearest road-edge segment to (px, py) within R (ties -> lowest world-local index), by
+// rings of grid cells around the point's cell.  Segments are keyed by the cell of their
+// first point, so a segment at distance d has its key within d + max_seg.  A key in a cell
+// r rings out is at least (r - 1) * cs away, so before ring r is searched every unseen
+// segment is at least (r - 1) * cs - max_seg away, and the search stops once that exceeds
+// the best distance found (or the radius).
+__device__ EdgeChoice nearest_edge(const WorldGrid &g, const int *ecs, const float4 *es,
+                                   const int *eid, float px, float py, float R) {
+    EdgeChoice ch{-1, -1.0f};
+    if (g.n_edge == 0 || !(px == px) || !(py == py)) return ch;
+    const float fx = floorf((px - g.ox) * g.inv_cs), fy = floorf((py - g.oy) * g.inv_cs);
+    // the point's (unclamped) cell, kept in a range where the ring loop stays short
+    const int cx = (int)fminf(fmaxf(fx, -1.0e6f), 1.0e6f);
+    const int cy = (int)fminf(fmaxf(fy, -1.0e6f), 1.0e6f);
+    const int rmax = (int)ceilf((R + g.max_seg) * g.inv_cs) + 1;
+    float best = INFINITY;
+    int bestk = 0x7fffffff;
+    for (int r = 0; r <= rmax; r++) {
+        if (best <= R && best + g.max_seg + 1e-3f * g.cs < (float)(r - 1) * g.cs) break;
+        // ring r: rows cy-r .. cy+r; full rows at the top and bottom, two cells otherwise
+        const int y0 = max(cy - r, 0), y1 = min(cy + r, g.ny - 1);
+        for (int yy = y0; yy <= y1; yy++) {
+            const bool edge_row = (yy == cy - r) || (yy == cy + r);
+            const int xa = cx - r, xb = cx + r;
+            for (int side = 0; side < (edge_row ? 1 : 2); side++) {
+                int x0, x1;
+                if (edge_row) {
+                    x0 = max(xa, 0);
+                    x1 = min(xb, g.nx - 1);
+                } else {
+                    x0 = x1 = side == 0 ? xa : xb;
+                    if (x0 < 0 || x0 >= g.nx) continue;
+                }
+                if (x0 > x1) continue;
+                const int q0 = ecs[yy * g.nx + x0], q1 = ecs[yy * g.nx + x1 + 1];
+                for (int q = q0; q < q1; q++) {
+                    const float4 e = es[q];
+                    const float ex = e.z - e.x, ey = e.w - e.y;
+                    const float ax = e.x - px, ay = e.y - py;
+                    const float ee = ex * ex + ey * ey;
+                    float u = ee > 0.0f ? -(ax * ex + ay * ey) / ee : 0.0f;
+                    u = fminf(fmaxf(u, 0.0f), 1.0f);
+                    const float qx = ax + u * ex, qy = ay + u * ey;
+                    const float d = sqrtf(qx * qx + qy * qy);
+                    const int k = eid[q];
+                    if (d < best || (d == best && k < bestk)) {
+                        best = d;
+                        bestk = k;
+                        ch.q = q;
+                    }
+                }
+            }
+        }
+    }
+    if (!(best <= R)) {
+        ch.q = -1;
+        return ch;
+    }
+    const float4 e = es[ch.q];
+    const float cr = (e.z - e.x) * (py - e.y) - (e.w - e.y) * (px - e.x);
+    ch.side = cr < 0.0f ? 1.0f : -1.0f;
+    return ch;
 }
 
-hipError_t launch_rollout_bwd_impl(const SimArgs &, const float2 *, const float *, int, int,
-                                   const float *, float2 *, float *, hipStream_t) {
-    return hipErrorNotSupported;
+__device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))); }
+__device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+__device__ __forceinline__ void bicycle_r(float &x, float &y, float &yaw, float &v, float L,
+                                          float acc, float steer, float dt, float vmax) {
+    float vb = fminf(fmaxf(v + 0.5f * acc * dt, -vmax), vmax);
+    float ts = tanf(steer);
+    float beta = atanf(0.5f * ts);
+    float sp, cp;
+    sincosf(yaw + beta, &sp, &cp);
+    float cb = cosf(beta);
+    x = x + vb * cp * dt;
+    y = y + vb * sp * dt;
+    yaw = yaw + vb * cb * ts / L * dt;
+    v = fminf(fmaxf(v + acc * dt, -vmax), vmax);
+}
+
+// smooth reward at (x, y, yaw) for a fixed segment choice, computed through the ego frame
+__device__ __forceinline__ float smooth_reward(float x, float y, float yaw, float gx, float gy,
+                                               const float4 *es, const EdgeChoice &ch, float R) {
+    float st, ct;
+    sincosf(yaw, &st, &ct);
+    const float dxg = gx - x, dyg = gy - y;
+    const float gpx = ct * dxg + st * dyg, gpy = -st * dxg + ct * dyg;
+    const float ng = sqrtf(gpx * gpx + gpy * gpy);
+    float s = -R;
+    if (ch.q >= 0) {
+        const float4 e = es[ch.q];
+        const float ax = e.x - x, ay = e.y - y, bx = e.z - x, by = e.w - y;
+        const float apx = ct * ax + st * ay, apy = -st * ax + ct * ay;
+        const float bpx = ct * bx + st * by, bpy = -st * bx + ct * by;
+        const float ex = bpx - apx, ey = bpy - apy;
+        const float ee = ex * ex + ey * ey;
+        float u = ee > 0.0f ? -(apx * ex + apy * ey) / ee : 0.0f;
+        u = fminf(fmaxf(u, 0.0f), 1.0f);
+        const float qx = apx + u * ex, qy = apy + u * ey;
+        s = ch.side * sqrtf(qx * qx + qy * qy);
+    }
+    return -ng - softplusf(s);
+}
+
+__device__ __forceinline__ void world_of(const int *agent_off, int W, int i, int &w) {
+    int lo = 0, hi = W - 1;  // largest w with agent_off[w] <= i
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (agent_off[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    w = lo;
+}
+
+__global__ __launch_bounds__(kRollThreads) void k_rollout_fwd(SimArgs a, const float2 *__restrict__ act,
+                                                              int T, int C, float *__restrict__ rewards,
+                                                              float *__restrict__ ckpt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.A) return;
+    int w;
+    world_of(a.agent_off, a.W, i, w);
+    const WorldGrid g = a.grid[w];
+    const int r0 = a.road_off[w];
+    const int *ecs = a.ecell_start + (size_t)w * kCellStride;
+    const float4 *es = a.eseg + r0;
+    const int *eid = a.eseg_id + r0;
+    float x = a.x[i], y = a.y[i], yaw = a.yaw[i], v = a.v[i];
+    const float L = a.len[i], gx = a.gx[i], gy = a.gy[i];
+    const size_t A = (size_t)a.A;
+    for (int t = 0; t < T; t++) {
+        if (t % C == 0) {
+            float *ck = ckpt + (size_t)(t / C) * 4 * A;
+            ck[i] = x;
+            ck[A + i] = y;
+            ck[2 * A + i] = yaw;
+            ck[3 * A + i] = v;
+        }
+        const float2 u = act[(size_t)t * A + i];
+        bicycle_r(x, y, yaw, v, L, u.x, u.y, a.dt, a.vmax);
+        const EdgeChoice ch = nearest_edge(g, ecs, es, eid, x, y, a.R_obs);
+        rewards[(size_t)t * A + i] = smooth_reward(x, y, yaw, gx, gy, es, ch, a.R_obs);
+    }
+}
+
+__global__ __launch_bounds__(kRollThreads) void k_rollout_bwd(SimArgs a, const float2 *__restrict__ act,
+                                                              const float *__restrict__ ckpt, int T, int C,
+                                                              const float *__restrict__ grad_r,
+                                                              float2 *__restrict__ grad_a,
+                                                              float *__restrict__ grad_s0) {
+    // per thread: states before steps c0..c0+C (C+1 entries) and the segment choice of the
+    // reward after each of the C steps
+    __shared__ float4 s_state[kRollThreads * (kMaxCkpt + 1)];
+    __shared__ int s_q[kRollThreads * kMaxCkpt];
+    __shared__ float s_side[kRollThreads * kMaxCkpt];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.A) return;
+    const int tid = threadIdx.x;
+    float4 *st = s_state + tid * (kMaxCkpt + 1);
+    int *sq = s_q + tid * kMaxCkpt;
+    float *ss = s_side + tid * kMaxCkpt;
+    int w;
+    world_of(a.agent_off, a.W, i, w);
+    const WorldGrid g = a.grid[w];
+    const int r0 = a.road_off[w];
+    const int *ecs = a.ecell_start + (size_t)w * kCellStride;
+    const float4 *es = a.eseg + r0;
+    const int *eid = a.eseg_id + r0;
+    const float L = a.len[i], gxa = a.gx[i], gya = a.gy[i];
+    const float dt = a.dt, vmax = a.vmax;
+    const size_t A = (size_t)a.A;
+    float lx = 0.f, ly = 0.f, lth = 0.f, lv = 0.f;  // adjoint of the state after the current step
+    const int nseg = (T + C - 1) / C;
+    for (int sgi = nseg - 1; sgi >= 0; sgi--) {
+        const int c0 = sgi * C;
+        const int c1 = min(T, c0 + C);
+        // recompute the segment forward
+        const float *ck = ckpt + (size_t)sgi * 4 * A;
+        float x = ck[i], y = ck[A + i], yaw = ck[2 * A + i], v = ck[3 * A + i];
+        st[0] = make_float4(x, y, yaw, v);
+        for (int t = c0; t < c1; t++) {
+            const float2 u = act[(size_t)t * A + i];
+            bicycle_r(x, y, yaw, v, L, u.x, u.y, dt, vmax);
+            st[t - c0 + 1] = make_float4(x, y, yaw, v);
+            const EdgeChoice ch = nearest_edge(g, ecs, es, eid, x, y, a.R_obs);
+            sq[t - c0] = ch.q;
+            ss[t - c0] = ch.side;
+        }
+        // reverse
+        for (int t = c1 - 1; t >= c0; t--) {
+            const float gr = grad_r[(size_t)t * A + i];
+            const float4 s1 = st[t - c0 + 1];
+            float sn, cs;
+            sincosf(s1.z, &sn, &cs);
+            // goal term: r = -|g'|
+            {
+                const float dxg = gxa - s1.x, dyg = gya - s1.y;
+                const float gpx = cs * dxg + sn * dyg, gpy = -sn * dxg + cs * dyg;
+                const float ng = sqrtf(gpx * gpx + gpy * gpy);
+                if (ng > 0.0f) {
+                    const float bgx = -gpx / ng * gr, bgy = -gpy / ng * gr;
+                    lx += -cs * bgx + sn * bgy;
+                    ly += -sn * bgx - cs * bgy;
+                    lth += gpy * bgx - gpx * bgy;
+                }
+            }
+            // off-road term: r = -softplus(side * |q'|), q' = a' + u e' in the ego frame
+            const int q = sq[t - c0];
+            if (q >= 0) {
+                const float side = ss[t - c0];
+                const float4 e = es[q];
+                const float ax = e.x - s1.x, ay = e.y - s1.y, bx = e.z - s1.x, by = e.w - s1.y;
+                const float apx = cs * ax + sn * ay, apy = -sn * ax + cs * ay;
+                const float bpx = cs * bx + sn * by, bpy = -sn * bx + cs * by;
+                const float ex = bpx - apx, ey = bpy - apy;
+                const float ee = ex * ex + ey * ey;
+                float u = ee > 0.0f ? -(apx * ex + apy * ey) / ee : 0.0f;
+                const bool cl = u <= 0.0f || u >= 1.0f;
+                u = fminf(fmaxf(u, 0.0f), 1.0f);
+                const float qx = apx + u * ex, qy = apy + u * ey;
+                const float d = sqrtf(qx * qx + qy * qy);
+                const float sdist = side * d;
+                const float sbar = -sigmoidf(sdist) * gr;
+                const float dbar = side * sbar;
+                float bqx = 0.f, bqy = 0.f;
+                if (d > 0.0f) {
+                    bqx = dbar * qx / d;
+                    bqy = dbar * qy / d;
+                }
+                float bapx = bqx, bapy = bqy, bex = u * bqx, bey = u * bqy;
+                if (!cl && ee > 0.0f) {
+                    const float ubar = bqx * ex + bqy * ey;
+                    bapx += ubar * (-ex / ee);
+                    bapy += ubar * (-ey / ee);
+                    bex += ubar * (-apx / ee - 2.0f * u * ex / ee);
+                    bey += ubar * (-apy / ee - 2.0f * u * ey / ee);
+                }
+                const float bbpx = bex, bbpy = bey;
+                bapx -= bex;
+                bapy -= bey;
+                const float bax = cs * bapx - sn * bapy, bay = sn * bapx + cs * bapy;
+                const float bbx = cs * bbpx - sn * bbpy, bby = sn * bbpx + cs * bbpy;
+                lx += -(bax + bbx);
+                ly += -(bay + bby);
+                lth += bapx * apy - bapy * apx + bbpx * bpy - bbpy * bpx;
+            }
+            // dynamics s_t -> s_{t+1}
+            const float4 s0 = st[t - c0];
+            const float2 u = act[(size_t)t * A + i];
+            const float vb_raw = s0.w + 0.5f * u.x * dt;
+            const float vb = fminf(fmaxf(vb_raw, -vmax), vmax);
+            const float c1f = (vb_raw > -vmax && vb_raw < vmax) ? 1.0f : 0.0f;
+            const float vn_raw = s0.w + u.x * dt;
+            const float c2f = (vn_raw > -vmax && vn_raw < vmax) ? 1.0f : 0.0f;
+            const float tdl = tanf(u.y), beta = atanf(0.5f * tdl);
+            const float cb = cosf(beta), sbt = sinf(beta);
+            const float sec2 = 1.0f + tdl * tdl;
+            const float dbeta = 0.5f * sec2 / (1.0f + 0.25f * tdl * tdl);
+            float sp, cp;
+            sincosf(s0.z + beta, &sp, &cp);
+            const float bvb = lx * cp * dt + ly * sp * dt + lth * cb * tdl / L * dt;
+            const float bphi = -lx * vb * sp * dt + ly * vb * cp * dt;
+            const float bth = lth + bphi;
+            const float bbeta = bphi - lth * vb * sbt * tdl / L * dt;
+            const float bdl = lth * vb * cb * sec2 / L * dt + bbeta * dbeta;
+            const float bv = bvb * c1f + lv * c2f;
+            const float ba = bvb * c1f * 0.5f * dt + lv * c2f * dt;
+            grad_a[(size_t)t * A + i] = make_float2(ba, bdl);
+            lth = bth;
+            lv = bv;
+        }
+    }
+    if (grad_s0) {
+        grad_s0[i] = lx;
+        grad_s0[A + i] = ly;
+        grad_s0[2 * A + i] = lth;
+        grad_s0[3 * A + i] = lv;
+    }
+}
+
+hipError_t launch_rollout_fwd_impl(const SimArgs &a, const float2 *actions, int T, int C,
+                                   float *rewards, float *ckpt, hipStream_t s) {
+    if (C < 1 || C > kMaxCkpt) return hipErrorInvalidValue;
+    const int blocks = (a.A + kRollThreads - 1) / kRollThreads;
+    hipLaunchKernelGGL(k_rollout_fwd, dim3(blocks), dim3(kRollThreads), 0, s, a, actions, T, C, rewards, ckpt);
+    return hipGetLastError();
+}
+
+hipError_t launch_rollout_bwd_impl(const SimArgs &a, const float2 *actions, const float *ckpt, int T,
+                                   int C, const float *grad_rewards, float2 *grad_actions,
+                                   float *grad_state0, hipStream_t s) {
+    if (C < 1 || C > kMaxCkpt) return hipErrorInvalidValue;
+    const int blocks = (a.A + kRollThreads - 1) / kRollThreads;
+    hipLaunchKernelGGL(k_rollout_bwd, dim3(blocks), dim3(kRollThreads), 0, s, a, actions, ckpt, T, C,
+                       grad_rewards, grad_actions, grad_state0);
+    return hipGetLastError();
 }
 
 }  // namespace gdk

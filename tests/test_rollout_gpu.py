@@ -1,0 +1,99 @@
+"""Differentiable rollout on the GPU against the FP64 oracle: rewards of the forward pass,
+the hand-written backward kernel against the oracle's vector-Jacobian product (which the
+CPU suite pins to central finite differences), checkpoint-independence of the gradient,
+and the torch.autograd.Function wrapper.
+
+Agents whose trajectory passes within 1e-3 m of a switch of a held-constant choice
+(nearest segment across a non-smooth boundary, clip activity, radius entry) are excluded
+and counted; the binary32 rollout and the FP64 oracle may take different branches there."""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-3
+
+
+def _setup(worlds=4, T=20):
+    from paper_2408_01584_amd import scenes as S
+    from paper_2408_01584_amd.sim import Sim
+    sc = S.make_scene(3, worlds=worlds)
+    acts = S.make_actions(3, T, sc.num_agents)
+    return sc, acts, Sim(sc)
+
+
+def _rel_err(g, o, floor):
+    return np.abs(g - o) / np.maximum(np.abs(o), floor)
+
+
+def test_rollout_forward_matches_oracle(gpu, oracle_mod):
+    sc, acts, sim = _setup()
+    rew, ckpt = sim.rollout_fwd(torch.as_tensor(acts, device="cuda"), 10)
+    g = rew.cpu().numpy()
+    o = oracle_mod.OracleSim(sc).rollout(acts.astype(np.float64), tol=1e-3)
+    ok = o["unstable"] == 0
+    assert ok.mean() > 0.8, ok.mean()
+    err = _rel_err(g[:, ok], o["rewards"][:, ok], 1.0)
+    assert err.max() < 1e-4, err.max()
+    # checkpoints hold the state before steps 0 and 10
+    ck = ckpt.cpu().numpy()
+    np.testing.assert_array_equal(ck[0, 0], sc.x)
+    np.testing.assert_allclose(ck[1], o["states"][10], rtol=1e-5, atol=1e-4)
+    print("rollout fwd: %d/%d agents compared, max rel err %.2e" % (ok.sum(), ok.size, err.max()))
+
+
+def test_rollout_backward_matches_oracle_vjp(gpu, oracle_mod):
+    sc, acts, sim = _setup()
+    T, A = acts.shape[0], sc.num_agents
+    gr = np.random.default_rng(3).uniform(0.5, 1.5, (T, A)).astype(np.float32)
+    a_t = torch.as_tensor(acts, device="cuda")
+    _, ckpt = sim.rollout_fwd(a_t, 10)
+    ga, g0 = sim.rollout_bwd(a_t, ckpt, torch.as_tensor(gr, device="cuda"), 10, want_state0=True)
+    orc = oracle_mod.OracleSim(sc)
+    o = orc.rollout(acts.astype(np.float64), tol=1e-3)
+    oga, og0 = orc.rollout_vjp(acts.astype(np.float64), gr.astype(np.float64))
+    ok = o["unstable"] == 0
+    ga, g0 = ga.cpu().numpy(), g0.cpu().numpy()
+    # per-agent relative error of the gradient vector (norm-wise)
+    num = np.linalg.norm((ga - oga)[:, ok].transpose(1, 0, 2).reshape(ok.sum(), -1), axis=1)
+    den = np.linalg.norm(oga[:, ok].transpose(1, 0, 2).reshape(ok.sum(), -1), axis=1)
+    rel = num / np.maximum(den, 1e-6)
+    assert rel.max() < REL, rel.max()
+    rel0 = np.linalg.norm(g0[:, ok] - og0[:, ok], axis=0) / np.maximum(np.linalg.norm(og0[:, ok], axis=0), 1e-6)
+    assert rel0.max() < REL, rel0.max()
+    print("rollout bwd: %d/%d agents, max per-agent rel err %.2e (state0 %.2e)" %
+          (ok.sum(), ok.size, rel.max(), rel0.max()))
+
+
+def test_checkpoint_interval_does_not_change_gradients(gpu):
+    sc, acts, sim = _setup(worlds=2)
+    T, A = acts.shape[0], sc.num_agents
+    a_t = torch.as_tensor(acts, device="cuda")
+    gr = torch.ones((T, A), device="cuda")
+    outs = []
+    for C in (1, 7, 10, 20):
+        rew, ck = sim.rollout_fwd(a_t, C)
+        ga, _ = sim.rollout_bwd(a_t, ck, gr, C)
+        outs.append((rew.cpu().numpy(), ga.cpu().numpy()))
+    for r, g in outs[1:]:
+        assert np.array_equal(r, outs[0][0]) and np.array_equal(g, outs[0][1])
+
+
+def test_autograd_function(gpu):
+    from paper_2408_01584_amd.sim import DiffRollout
+    sc, acts, sim = _setup(worlds=2)
+    a_t = torch.as_tensor(acts, device="cuda").requires_grad_(True)
+    rew = DiffRollout.apply(a_t, sim, 10)
+    w = torch.linspace(0.5, 1.5, rew.numel(), device="cuda").reshape(rew.shape)
+    (rew * w).sum().backward()
+    _, ck = sim.rollout_fwd(a_t.detach(), 10)
+    ga, _ = sim.rollout_bwd(a_t.detach(), ck, w, 10)
+    assert torch.equal(a_t.grad, ga)
+
+
+def test_rollout_leaves_state_untouched(gpu):
+    sc, acts, sim = _setup(worlds=2)
+    before = sim.host_outputs()["state"]
+    sim.rollout_fwd(torch.as_tensor(acts, device="cuda"), 10)
+    assert np.array_equal(before, sim.host_outputs()["state"])
