@@ -99,12 +99,13 @@ typedef struct {
     float collision_penalty;   /* reward -= penalty when the agent collided */
     float cell_size;           /* road grid cell (m); 0 = library default (10 m) */
     int32_t obs_waves;         /* launch shape of the step kernel: waves per workgroup
-                                  (1, 2, 4, 8, 12, 16; 0 = default 16, reduced until the
-                                  workgroup fits the LDS) */
+                                  (1, 2, 4, 8, 12, 16; 0 = the shape with the most
+                                  resident waves per compute unit that fits the LDS) */
     int32_t obs_bins;          /* distance bins of the top-K selection (64, 128, 256,
                                   512; 0 = default) */
     int32_t obs_cands;         /* candidate-list entries per wave of the top-K selection
-                                  (0 = default 1024; agents with more candidates rescan) */
+                                  (128, 256, 384, 512, 768, 1024; 0 = chosen with
+                                  obs_waves; agents with more candidates rescan the grid) */
     int32_t reserved[2];       /* must be zero */
 } gd_config;
 

@@ -130,7 +130,9 @@ static gd_status check_config(const gd_config *c, const int32_t *h_agent_off,
     if (!(c->obs_bins == 0 || c->obs_bins == 64 || c->obs_bins == 128 || c->obs_bins == 256 ||
           c->obs_bins == 512))
         return fail(GD_E_ARG, "obs_bins must be 0, 64, 128, 256 or 512");
-    if (c->obs_cands < 0 || c->obs_cands > 4096) return fail(GD_E_ARG, "obs_cands must be in [0, 4096]");
+    if (!(c->obs_cands == 0 || c->obs_cands == 128 || c->obs_cands == 256 || c->obs_cands == 384 ||
+          c->obs_cands == 512 || c->obs_cands == 768 || c->obs_cands == 1024))
+        return fail(GD_E_ARG, "obs_cands must be 0, 128, 256, 384, 512, 768 or 1024");
     if (c->reserved[0] || c->reserved[1]) return fail(GD_E_ARG, "reserved fields must be zero");
     const int W = c->num_worlds;
     if (h_agent_off[0] != 0 || h_road_off[0] != 0) return fail(GD_E_ARG, "offsets must start at 0");
@@ -156,25 +158,43 @@ static long long partner_slots_of(const gd_config *c, const int32_t *h_agent_off
 }
 
 // Launch shape of the fused step: waves per workgroup, distance bins, LDS staging of the
-// road and size of the per-wave candidate list, shrunk until a workgroup fits the LDS.
+// road and size of the per-wave candidate list.  Among the shapes that fit, the one with
+// the most resident waves per compute unit wins (workgroups per CU by LDS, at most 24
+// waves per CU by registers), then the larger candidate list; explicit values in the
+// configuration restrict the search.
 static bool launch_shape(const gd_config *c, int max_road, int max_agents, int &waves, int &bins,
                          int &road_cap, int &cand_cap) {
     bins = c->obs_bins ? c->obs_bins : 256;
-    const int want_waves = c->obs_waves ? c->obs_waves : 16;
-    const int want_cands = c->obs_cands ? c->obs_cands : 1024;
     const int K = c->top_k;
     const int agent_cap = std::max(max_agents, 1);
+    const int wave_opts[] = {16, 12, 8, 4, 2, 1};
+    const int cand_opts[] = {1024, 768, 512, 384, 256, 128};
     for (int staged = 1; staged >= 0; staged--) {
         if (staged && K == 0) continue;
-        road_cap = staged ? std::max(max_road, 1) : 0;
-        for (int cc = want_cands; cc >= 128; cc /= 2) {
-            for (int wv = want_waves; wv >= 1; wv = (wv > 8 ? wv - 4 : wv / 2)) {
-                if (step_lds_bytes(wv, bins, K, K ? cc : 0, road_cap, agent_cap) <= (size_t)kLdsBytes) {
-                    waves = wv;
-                    cand_cap = K ? cc : 0;
-                    return true;
+        const int rc = staged ? std::max(max_road, 1) : 0;
+        if (staged && rc > 60000) continue;
+        int best_res = 0, best_w = 0, best_c = 0;
+        for (int wv : wave_opts) {
+            if (c->obs_waves && wv != c->obs_waves) continue;
+            for (int cc : cand_opts) {
+                if (c->obs_cands && cc != c->obs_cands) continue;
+                const size_t lds = step_lds_bytes(wv, bins, K, K ? cc : 0, rc, agent_cap);
+                if (lds > (size_t)kLdsBytes) continue;
+                const int per_cu = std::min((int)((size_t)kLdsBytes / lds) * wv, 24);
+                // prefer resident waves, then whole-list candidate capacity (>= 512)
+                const int score = per_cu * 4 + (cc >= 768 ? 2 : 0) + (cc >= 512 ? 1 : 0);
+                if (score > best_res) {
+                    best_res = score;
+                    best_w = wv;
+                    best_c = cc;
                 }
             }
+        }
+        if (best_w) {
+            waves = best_w;
+            cand_cap = K ? best_c : 0;
+            road_cap = rc;
+            return true;
         }
     }
     return false;

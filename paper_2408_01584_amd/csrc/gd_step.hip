@@ -128,17 +128,30 @@ __device__ __forceinline__ int lane_prefix(unsigned long long mask) {
 
 __host__ __device__ inline int stage_cap(int K) { return ((K + 64 + 63) / 64) * 64; }
 
-// per-wave LDS: histogram NB ints | candidate list ccap ints | staging scap ints | perm K ushorts
-__host__ __device__ inline size_t wave_lds_bytes(int NB, int K, int ccap) {
-    size_t b = (size_t)NB * 4 + (size_t)ccap * 4 + (size_t)stage_cap(K) * 4 + (size_t)K * 2;
+// per-wave LDS: histogram NB ints | candidate list ccap indices | staging scap indices |
+// perm K ushorts.  Indices are 16-bit when the road is staged in LDS (a staged world has
+// far fewer than 65536 points), 32-bit otherwise.
+__host__ __device__ inline size_t wave_lds_bytes(int NB, int K, int ccap, int idx_bytes) {
+    size_t b = (size_t)NB * 4 + (size_t)ccap * idx_bytes + (size_t)stage_cap(K) * idx_bytes +
+               (size_t)K * 2;
     return (b + 15) / 16 * 16;
 }
+
+template <bool STAGED>
+struct LdsIndex {
+    using type = int;
+};
+template <>
+struct LdsIndex<true> {
+    using type = unsigned short;
+};
 
 constexpr int kAgentArrays = 10;  // x y yaw v L W cos sin flags coll
 
 template <int NB, bool STAGED>
 __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     extern __shared__ __align__(16) unsigned char smem[];
+    using idx_t = typename LdsIndex<STAGED>::type;
     constexpr int BPL = NB / kWave;  // bins per lane
     const int w = c.order ? c.order[blockIdx.x] : (int)blockIdx.x;
     const int tid = threadIdx.x;
@@ -164,10 +177,10 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     int *sf = reinterpret_cast<int *>(sag + 8 * ac);
     int *scoll = reinterpret_cast<int *>(sag + 9 * ac);
     unsigned char *mine = reinterpret_cast<unsigned char *>(sag + kAgentArrays * ac) +
-                          (size_t)wid * wave_lds_bytes(NB, K, ccap);
+                          (size_t)wid * wave_lds_bytes(NB, K, ccap, (int)sizeof(idx_t));
     int *hist = reinterpret_cast<int *>(mine);
-    int *cand = hist + NB;
-    int *stage = cand + ccap;
+    idx_t *cand = reinterpret_cast<idx_t *>(hist + NB);
+    idx_t *stage = cand + ccap;
     unsigned short *perm = reinterpret_cast<unsigned short *>(stage + scap);
 
     // phase 0: the world's road points into LDS (consumed in phase 5)
@@ -224,8 +237,9 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             if (sat_box_box(dx, dy, sc[i], ss[i], sL[i], sW[i], sc[j], ss[j], sL[j], sW[j]) < 0.0f)
                 atomicOr(&scoll[i], (int)GD_FLAG_COLL_AGENT);
         }
-        // phase 2b: road edges, one wave per agent, lanes over the segments of the cells
-        // under the box (segments are keyed by their first point: widen by max_seg)
+        // phase 2b: road edges, one wave per agent, lanes over the segments keyed in the
+        // grid cells under the box (segments are keyed by their first point: widen by the
+        // longest segment)
         {
             const WorldGrid g = a.grid[w];
             const int *ecs = a.ecell_start + (size_t)w * kCellStride;
@@ -410,26 +424,30 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
         if (lane < nrows) row_span(g, cst, rlo + lane, px, py, R, marg, sq0, sq1);
         wave_sync();
 
-        // b. one scan: candidate list + histogram of bin(d2)
+        // b. one scan: candidate list + histogram of bin(d2); two chunks of 64 points per
+        //    iteration so that both LDS loads are in flight together
         int ncand = 0;
         for (int rr = 0; rr < nrows; rr++) {
             const int q0 = __builtin_amdgcn_readlane(sq0, rr);
             const int q1 = __builtin_amdgcn_readlane(sq1, rr);
-            for (int base = q0; base < q1; base += kWave) {
-                const int q = base + lane;
-                bool in = false;
-                if (q < q1) {
-                    const float2 p = rxy[q];
-                    const float k = key32(px, py, p.x, p.y);
-                    if (k <= R2) {
-                        in = true;
-                        atomicAdd(&hist[bin_of(k, bscale, NB)], 1);
-                    }
-                }
-                const unsigned long long bal = __ballot(in);
-                const int pos = ncand + lane_prefix(bal);
-                if (in && pos < ccap) cand[pos] = q;
-                ncand += __popcll(bal);
+            for (int base = q0; base < q1; base += 2 * kWave) {
+                const int qa = base + lane, qb = base + kWave + lane;
+                const float2 pa = rxy[min(qa, q1 - 1)];
+                const float2 pb = rxy[min(qb, q1 - 1)];
+                const float ka = key32(px, py, pa.x, pa.y);
+                const float kb = key32(px, py, pb.x, pb.y);
+                const bool ina = qa < q1 && ka <= R2;
+                const bool inb = qb < q1 && kb <= R2;
+                if (ina) atomicAdd(&hist[bin_of(ka, bscale, NB)], 1);
+                if (inb) atomicAdd(&hist[bin_of(kb, bscale, NB)], 1);
+                const unsigned long long bala = __ballot(ina);
+                const unsigned long long balb = __ballot(inb);
+                const int posa = ncand + lane_prefix(bala);
+                const int na = __popcll(bala);
+                const int posb = ncand + na + lane_prefix(balb);
+                if (ina && posa < ccap) cand[posa] = (idx_t)qa;
+                if (inb && posb < ccap) cand[posb] = (idx_t)qb;
+                ncand += na + __popcll(balb);
             }
         }
         wave_sync();
@@ -487,7 +505,7 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
                 const float2 p = rxy[q];
                 const float k = key32(px, py, p.x, p.y);
                 const int b = bin_of(k, bscale, NB);
-                if (b < bstar || (b == bstar && !overflow)) stage[atomicAdd(&hist[b], 1)] = q;
+                if (b < bstar || (b == bstar && !overflow)) stage[atomicAdd(&hist[b], 1)] = (idx_t)q;
             }
         } else {
             for (int rr = 0; rr < nrows; rr++) {
@@ -500,7 +518,8 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
                         const float k = key32(px, py, p.x, p.y);
                         if (k <= R2) {
                             const int b = bin_of(k, bscale, NB);
-                            if (b < bstar || (b == bstar && !overflow)) stage[atomicAdd(&hist[b], 1)] = q;
+                            if (b < bstar || (b == bstar && !overflow))
+                                stage[atomicAdd(&hist[b], 1)] = (idx_t)q;
                         }
                     }
                 }
@@ -594,8 +613,9 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
 }
 
 size_t step_lds_bytes(int waves, int NB, int K, int ccap, int road_cap, int agent_cap) {
+    const int idx_bytes = road_cap > 0 ? 2 : 4;
     return (size_t)road_cap * 8 + (size_t)agent_cap * 4 * kAgentArrays +
-           (size_t)waves * wave_lds_bytes(NB, K, ccap);
+           (size_t)waves * wave_lds_bytes(NB, K, ccap, idx_bytes);
 }
 
 // raise the kernel's dynamic-LDS limit to what this launch needs (once per size increase)

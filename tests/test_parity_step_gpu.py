@@ -47,7 +47,7 @@ def test_cfg2_uneven_subset(gpu, oracle_mod):
     print("cfg2 subset:", st)
 
 
-@pytest.mark.parametrize("waves,bins,cands", [(1, 64, 256), (4, 128, 512), (16, 512, 1024), (2, 256, 128)])
+@pytest.mark.parametrize("waves,bins,cands", [(1, 64, 256), (4, 128, 512), (16, 512, 1024), (2, 256, 128), (12, 256, 768)])
 def test_launch_shapes_bitwise_equal(gpu, waves, bins, cands):
     """Every launch shape of the observation kernel gives the same bits."""
     from paper_2408_01584_amd import scenes as S
