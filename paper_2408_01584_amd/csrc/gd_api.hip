@@ -162,31 +162,36 @@ static long long partner_slots_of(const gd_config *c, const int32_t *h_agent_off
 // the most resident waves per compute unit wins (workgroups per CU by LDS, at most 24
 // waves per CU by registers), then the larger candidate list; explicit values in the
 // configuration restrict the search.
-static bool launch_shape(const gd_config *c, int max_road, int max_agents, int &waves, int &bins,
-                         int &road_cap, int &cand_cap) {
+static bool launch_shape(const gd_config *c, int max_road, int max_cells, int max_edges,
+                         int max_agents, int &waves, int &bins, int &road_cap, int &edge_cap,
+                         int &cand_cap) {
     bins = c->obs_bins ? c->obs_bins : 256;
     const int K = c->top_k;
     const int agent_cap = std::max(max_agents, 1);
+    const int cell_cap4 = (max_cells + 1 + 3) / 4 * 4;
     const int wave_opts[] = {16, 12, 8, 4, 2, 1};
     const int cand_opts[] = {1024, 768, 512, 384, 256, 128};
     for (int staged = 1; staged >= 0; staged--) {
         if (staged && K == 0) continue;
         const int rc = staged ? std::max(max_road, 1) : 0;
         if (staged && rc > 60000) continue;
-        int best_res = 0, best_w = 0, best_c = 0;
-        for (int wv : wave_opts) {
-            if (c->obs_waves && wv != c->obs_waves) continue;
-            for (int cc : cand_opts) {
-                if (c->obs_cands && cc != c->obs_cands) continue;
-                const size_t lds = step_lds_bytes(wv, bins, K, K ? cc : 0, rc, agent_cap);
-                if (lds > (size_t)kLdsBytes) continue;
-                const int per_cu = std::min((int)((size_t)kLdsBytes / lds) * wv, 24);
-                // prefer resident waves, then whole-list candidate capacity (>= 512)
-                const int score = per_cu * 4 + (cc >= 768 ? 2 : 0) + (cc >= 512 ? 1 : 0);
-                if (score > best_res) {
-                    best_res = score;
-                    best_w = wv;
-                    best_c = cc;
+        int best_res = 0, best_w = 0, best_c = 0, best_e = 0;
+        for (int ec : {max_edges, 0}) {
+            for (int wv : wave_opts) {
+                if (c->obs_waves && wv != c->obs_waves) continue;
+                for (int cc : cand_opts) {
+                    if (c->obs_cands && cc != c->obs_cands) continue;
+                    const size_t lds = step_lds_bytes(wv, bins, K, K ? cc : 0, rc, cell_cap4, ec, agent_cap);
+                    if (lds > (size_t)kLdsBytes) continue;
+                    const int per_cu = std::min((int)((size_t)kLdsBytes / lds) * wv, 24);
+                    // prefer resident waves, then staged edges, then candidate capacity
+                    const int score = per_cu * 8 + (ec ? 4 : 0) + (cc >= 768 ? 2 : 0) + (cc >= 512 ? 1 : 0);
+                    if (score > best_res) {
+                        best_res = score;
+                        best_w = wv;
+                        best_c = cc;
+                        best_e = ec;
+                    }
                 }
             }
         }
@@ -194,6 +199,7 @@ static bool launch_shape(const gd_config *c, int max_road, int max_agents, int &
             waves = best_w;
             cand_cap = K ? best_c : 0;
             road_cap = rc;
+            edge_cap = best_e;
             return true;
         }
     }
@@ -342,10 +348,6 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
         max_road = std::max(max_road, h_road_off[w + 1] - h_road_off[w]);
         max_agents = std::max(max_agents, h_agent_off[w + 1] - h_agent_off[w]);
     }
-    int waves = 0, bins = 0, road_cap = 0, cand_cap = 0;
-    if (!launch_shape(cfg, max_road, max_agents, waves, bins, road_cap, cand_cap))
-        return fail(GD_E_SIZE, "no launch shape fits the LDS (top_k %d, %d agents per world)",
-                    cfg->top_k, max_agents);
     const std::vector<int> order = world_order(W, h_agent_off, h_road_off);
     hipStream_t s = (hipStream_t)stream;
     // device offsets must hold the host values
@@ -367,8 +369,6 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
     sim->h_agent_off.assign(h_agent_off, h_agent_off + W + 1);
     sim->h_road_off.assign(h_road_off, h_road_off + W + 1);
     sim->lay = L;
-    sim->waves = waves;
-    sim->bins = bins;
     sim->max_road = max_road;
     sim->max_agents = max_agents;
     sim->slots = S;
@@ -431,9 +431,7 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
     a.pbase = (long long *)(ws + L.pbase);
     a.err = (unsigned *)(ws + L.err);
     sim->ctl.order = (const int *)(ws + L.order);
-    sim->ctl.road_cap = road_cap;
     sim->ctl.agent_cap = std::max(max_agents, 1);
-    sim->ctl.cand_cap = cand_cap;
 
     std::vector<long long> pb(W);
     long long acc = 0;
@@ -465,6 +463,36 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
     if ((e = hipStreamSynchronize(s)) != hipSuccess) {
         delete sim;
         return hip_fail(e, "grid build sync");
+    }
+    // launch shape: needs the largest grid of the batch (cell starts are staged in LDS)
+    {
+        std::vector<WorldGrid> grids(W);
+        if ((e = hipMemcpy(grids.data(), a.grid, sizeof(WorldGrid) * W, hipMemcpyDeviceToHost)) != hipSuccess) {
+            delete sim;
+            return hip_fail(e, "grid read-back");
+        }
+        int max_cells = 1, max_edges = 0;
+        for (const WorldGrid &g : grids) {
+            max_cells = std::max(max_cells, g.nx * g.ny);
+            max_edges = std::max(max_edges, g.n_edge);
+        }
+        int waves = 0, bins = 0, road_cap = 0, edge_cap = 0, cand_cap = 0;
+        if (!launch_shape(cfg, max_road, max_cells, max_edges, max_agents, waves, bins, road_cap,
+                          edge_cap, cand_cap)) {
+            delete sim;
+            return fail(GD_E_SIZE, "no launch shape fits the LDS (top_k %d, %d agents per world)",
+                        cfg->top_k, max_agents);
+        }
+        sim->waves = waves;
+        sim->bins = bins;
+        sim->ctl.road_cap = road_cap;
+        sim->ctl.cell_cap4 = (max_cells + 1 + 3) / 4 * 4;
+        sim->ctl.edge_cap = edge_cap;
+        sim->ctl.cand_cap = cand_cap;
+        // an identity order needs no indirection
+        bool identity = true;
+        for (int w = 0; w < W; w++) identity = identity && order[w] == w;
+        if (identity) sim->ctl.order = nullptr;
     }
     st = enqueue_step(sim, kModeReset, nullptr, nullptr, s);
     if (st != GD_OK) {

@@ -73,6 +73,9 @@ struct StepCtl {
     const uint8_t *mask;       // [W] worlds to reset (kModeReset; NULL = all)
     const int *order;          // [W] world of each workgroup (longest first), NULL = identity
     int road_cap;              // road points staged in LDS per world (0 = read from global)
+    int cell_cap4;             // LDS slots for a world's grid cell starts (max cells + 1,
+                               // rounded up to a multiple of 4)
+    int edge_cap;              // edge segments staged in LDS per world (0 = read from global)
     int agent_cap;             // agents per world held in LDS
     int cand_cap;              // candidate list entries per wave
 };
@@ -87,7 +90,8 @@ Layout make_layout(int W, long long A, long long R);
 // launchers (return hipError_t of the launch)
 hipError_t launch_build_grid(const SimArgs &a, float cell_size, hipStream_t s);
 hipError_t launch_step(const SimArgs &a, const StepCtl &c, int waves, int bins, hipStream_t s);
-size_t step_lds_bytes(int waves, int NB, int K, int ccap, int road_cap, int agent_cap);
+size_t step_lds_bytes(int waves, int NB, int K, int ccap, int road_cap, int cell_cap4,
+                      int edge_cap, int agent_cap);
 
 // ---------------------------------------------------------------- device helpers
 

@@ -82,8 +82,11 @@ __device__ __forceinline__ float sat_box_seg(float c, float s, float hL, float h
     return sep;
 }
 
+// LDS hand-off between the lanes of one wave.  A wave's LDS operations complete in
+// program order, so only the compiler has to be kept from reordering them: a
+// wavefront-scope fence does that without waiting for outstanding global stores.
 __device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
 
@@ -146,7 +149,7 @@ struct LdsIndex<true> {
     using type = unsigned short;
 };
 
-constexpr int kAgentArrays = 10;  // x y yaw v L W cos sin flags coll
+constexpr int kAgentArrays = 12;  // x y yaw v L W cos sin goal_x goal_y flags coll
 
 template <int NB, bool STAGED>
 __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
@@ -169,13 +172,20 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     const int S = a.P >= 0 ? a.P : (n > 0 ? n - 1 : 0);
     const int mode = c.mode;
 
+    // LDS: [road xy][road dir/index][cell starts] (staged worlds)
+    //      [edge segments][edge cell starts] (when they fit) [agents] [per-wave buffers]
     float2 *sroad = reinterpret_cast<float2 *>(smem);
-    float *sag = reinterpret_cast<float *>(smem + (STAGED ? (size_t)c.road_cap * 8 : 0));
+    float2 *saux = sroad + (STAGED ? c.road_cap : 0);
+    int *scells = reinterpret_cast<int *>(saux + (STAGED ? c.road_cap : 0));
+    float4 *sedge = reinterpret_cast<float4 *>(scells + (STAGED ? c.cell_cap4 : 0));
+    int *secells = reinterpret_cast<int *>(sedge + c.edge_cap);
+    float *sag = reinterpret_cast<float *>(secells + (c.edge_cap ? c.cell_cap4 : 0));
     const int ac = c.agent_cap;
     float *sx = sag, *sy = sag + ac, *syaw = sag + 2 * ac, *sv = sag + 3 * ac;
     float *sL = sag + 4 * ac, *sW = sag + 5 * ac, *sc = sag + 6 * ac, *ss = sag + 7 * ac;
-    int *sf = reinterpret_cast<int *>(sag + 8 * ac);
-    int *scoll = reinterpret_cast<int *>(sag + 9 * ac);
+    float *sgx = sag + 8 * ac, *sgy = sag + 9 * ac;
+    int *sf = reinterpret_cast<int *>(sag + 10 * ac);
+    int *scoll = reinterpret_cast<int *>(sag + 11 * ac);
     unsigned char *mine = reinterpret_cast<unsigned char *>(sag + kAgentArrays * ac) +
                           (size_t)wid * wave_lds_bytes(NB, K, ccap, (int)sizeof(idx_t));
     int *hist = reinterpret_cast<int *>(mine);
@@ -183,9 +193,23 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     idx_t *stage = cand + ccap;
     unsigned short *perm = reinterpret_cast<unsigned short *>(stage + scap);
 
-    // phase 0: the world's road points into LDS (consumed in phase 5)
-    if (STAGED && K > 0)
-        for (int k = tid; k < nr; k += bs) sroad[k] = a.pt_xy[r0 + k];
+    const WorldGrid g = a.grid[w];
+    const int ncell = g.nx * g.ny;
+    // phase 0: the world's cell-sorted road points and grid rows into LDS (phase 5), and
+    // its edge segments with their grid rows (phase 2b) when they fit
+    if (STAGED && K > 0) {
+        for (int k = tid; k < nr; k += bs) {
+            sroad[k] = a.pt_xy[r0 + k];
+            saux[k] = a.pt_aux[r0 + k];
+        }
+        const int *cs0 = a.cell_start + (size_t)w * kCellStride;
+        for (int k = tid; k <= ncell; k += bs) scells[k] = cs0[k];
+    }
+    if (c.edge_cap && mode == kModeStep) {
+        for (int k = tid; k < g.n_edge; k += bs) sedge[k] = a.eseg[r0 + k];
+        const int *ec0 = a.ecell_start + (size_t)w * kCellStride;
+        for (int k = tid; k <= ncell; k += bs) secells[k] = ec0[k];
+    }
 
     // phase 1: agents into LDS, dynamics of the alive ones
     int t = a.t[w];
@@ -196,8 +220,9 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             const int f = a.fl[gi];
             float x = a.x[gi], y = a.y[gi], yaw = a.yaw[gi], v = a.v[gi];
             const float L = a.len[gi];
+            // the action is read for every agent (no dependence on the flags load)
+            const float2 act = mode == kModeStep ? c.actions[gi] : make_float2(0.f, 0.f);
             if (mode == kModeStep && (f & GD_FLAG_ALIVE)) {
-                const float2 act = c.actions[gi];
                 if (!(isfinite(act.x) && isfinite(act.y))) nonfinite = true;
                 bicycle(x, y, yaw, v, L, act.x, act.y, a.dt, a.vmax);
                 a.x[gi] = x;
@@ -211,6 +236,8 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             sv[i] = v;
             sL[i] = L;
             sW[i] = a.wid[gi];
+            sgx[i] = a.gx[gi];
+            sgy[i] = a.gy[gi];
             float sn, cs;
             sincosf(yaw, &sn, &cs);
             sc[i] = cs;
@@ -241,9 +268,8 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
         // grid cells under the box (segments are keyed by their first point: widen by the
         // longest segment)
         {
-            const WorldGrid g = a.grid[w];
-            const int *ecs = a.ecell_start + (size_t)w * kCellStride;
-            const float4 *es = a.eseg + r0;
+            const int *ecs = c.edge_cap ? secells : a.ecell_start + (size_t)w * kCellStride;
+            const float4 *es = c.edge_cap ? sedge : a.eseg + r0;
             for (int i = wid; i < n; i += nwaves) {
                 if (!(sf[i] & GD_FLAG_ALIVE)) continue;
                 const float xi = sx[i], yi = sy[i], ci = sc[i], si = ss[i];
@@ -286,7 +312,7 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             bool done = true;
             if (f & GD_FLAG_ALIVE) {
                 out = scoll[i];
-                const bool goal = key32(sx[i], sy[i], a.gx[gi], a.gy[gi]) <= a.goal_r2;
+                const bool goal = key32(sx[i], sy[i], sgx[i], sgy[i]) <= a.goal_r2;
                 const bool coll = out != 0;
                 if (goal) out |= GD_FLAG_GOAL;
                 r = (goal ? 1.0f : 0.0f) - (coll ? a.penalty : 0.0f);
@@ -355,7 +381,7 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
         const int f = sf[i];
         float4 e0 = make_float4(0.f, 0.f, 0.f, 0.f), e1 = e0;
         if (f & GD_FLAG_VISIBLE) {
-            const float gdx = a.gx[gi] - sx[i], gdy = a.gy[gi] - sy[i];
+            const float gdx = sgx[i] - sx[i], gdy = sgy[i] - sy[i];
             e0 = make_float4(sv[i], sL[i], sW[i], sc[i] * gdx + ss[i] * gdy);
             e1 = make_float4(-ss[i] * gdx + sc[i] * gdy,
                              (!fresh && (f & GD_FLAG_COLL_AGENT)) ? 1.0f : 0.0f,
@@ -367,10 +393,9 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     }
 
     // phase 5: partners and road top-K, one wave per agent
-    const WorldGrid g = a.grid[w];
     const float2 *rxy = STAGED ? sroad : (a.pt_xy + r0);
-    const float2 *aux = a.pt_aux + r0;
-    const int *cst = a.cell_start + (size_t)w * kCellStride;
+    const float2 *aux = STAGED ? saux : (a.pt_aux + r0);
+    const int *cst = STAGED ? scells : (a.cell_start + (size_t)w * kCellStride);
     const float R = a.R_obs, R2 = a.R2_obs;
     const float bscale = (float)NB / R2;
     const float marg = 1e-3f * g.cs + 1e-3f;
@@ -612,9 +637,12 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     }
 }
 
-size_t step_lds_bytes(int waves, int NB, int K, int ccap, int road_cap, int agent_cap) {
+size_t step_lds_bytes(int waves, int NB, int K, int ccap, int road_cap, int cell_cap4,
+                      int edge_cap, int agent_cap) {
     const int idx_bytes = road_cap > 0 ? 2 : 4;
-    return (size_t)road_cap * 8 + (size_t)agent_cap * 4 * kAgentArrays +
+    const size_t staged = road_cap > 0 ? (size_t)road_cap * 16 + (size_t)cell_cap4 * 4 : 0;
+    const size_t edges = edge_cap > 0 ? (size_t)edge_cap * 16 + (size_t)cell_cap4 * 4 : 0;
+    return staged + edges + (size_t)agent_cap * 4 * kAgentArrays +
            (size_t)waves * wave_lds_bytes(NB, K, ccap, idx_bytes);
 }
 
@@ -633,7 +661,7 @@ static hipError_t prepare(size_t lds) {
 
 template <int NB, bool STAGED>
 static hipError_t launch_one(const SimArgs &a, const StepCtl &c, int waves, hipStream_t st) {
-    const size_t lds = step_lds_bytes(waves, NB, a.K, c.cand_cap, c.road_cap, c.agent_cap);
+    const size_t lds = step_lds_bytes(waves, NB, a.K, c.cand_cap, c.road_cap, c.cell_cap4, c.edge_cap, c.agent_cap);
     hipError_t e = prepare<NB, STAGED>(lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_step<NB, STAGED>), dim3(a.W), dim3(waves * kWave), lds, st, a, c);
@@ -643,7 +671,7 @@ static hipError_t launch_one(const SimArgs &a, const StepCtl &c, int waves, hipS
 template <int NB, bool STAGED>
 static bool node_one(const SimArgs *a, const StepCtl *c, int waves, hipKernelNodeParams &p,
                      void **args) {
-    const size_t lds = step_lds_bytes(waves, NB, a->K, c->cand_cap, c->road_cap, c->agent_cap);
+    const size_t lds = step_lds_bytes(waves, NB, a->K, c->cand_cap, c->road_cap, c->cell_cap4, c->edge_cap, c->agent_cap);
     if (prepare<NB, STAGED>(lds) != hipSuccess) return false;
     p.func = (void *)k_step<NB, STAGED>;
     p.gridDim = dim3(a->W);
