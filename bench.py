@@ -26,7 +26,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12  # MI355X HBM3E, B/s
-PMC_FILE = os.path.join(ROOT, "profiles", "road_obs_cfg1_counters.json")
+WORKLOAD_TAG = "256w_64a_4000r_k200"
+PMC_FILE = os.path.join(ROOT, "profiles", "k_step_%s_hbm_counters.json" % WORKLOAD_TAG)
+COPY_ELEMS = 1 << 28  # float32 elements of the calibration copy (1 GiB each way)
 
 
 def parse():
@@ -40,6 +42,9 @@ def parse():
     ap.add_argument("--no-graph", action="store_true", help="launch kernels directly, no HIP graph")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc output folders (FETCH_SIZE, WRITE_SIZE) of a "
+                         "--copy-calibration run into the HBM-traffic record, then exit")
     return ap.parse_args()
 
 
@@ -50,8 +55,55 @@ def source_digest(*names):
     return h.hexdigest()[:16]
 
 
+def _counter_rows(folder, counter):
+    """{dispatch id: (kernel name, value)} of one counter from a rocprofv3 --pmc folder."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit("no counter_collection.csv under %s" % folder)
+    out = {}
+    for f in files:
+        for row in csv.DictReader(open(f)):
+            if row["Counter_Name"] != counter:
+                continue
+            key = (f, row["Dispatch_Id"])
+            name, v = out.get(key, (row["Kernel_Name"], 0.0))
+            out[key] = (name, v + float(row["Counter_Value"]))
+    return out
+
+
+def ingest_counters(fetch_dir, write_dir):
+    """HBM bytes per k_step launch: FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each
+    scaled by what the same counter reads for the 1 GiB calibration copy."""
+    res = {}
+    for counter, folder in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = _counter_rows(folder, counter)
+        step = [v for n, v in rows.values() if "k_step" in n]
+        copies = [v for n, v in rows.values() if "copyBuffer" in n or "copy" in n.lower()]
+        if not step or not copies:
+            raise SystemExit("%s: k_step or copy dispatches missing" % counter)
+        big = max(copies)
+        calib = [v for v in copies if v > 0.5 * big]
+        ideal_kib = COPY_ELEMS * 4 / 1024.0
+        factor = (sum(calib) / len(calib)) / ideal_kib
+        res[counter] = {"kib_per_launch": sum(step) / len(step), "launches": len(step),
+                        "copy_kib": sum(calib) / len(calib), "copy_ideal_kib": ideal_kib,
+                        "factor": factor}
+    hbm = sum(r["kib_per_launch"] / r["factor"] for r in res.values()) * 1024.0
+    rec = {"kernel": "k_step", "workload": WORKLOAD_TAG,
+           "source_digest": source_digest("gd_step.hip", "gd_internal.h"),
+           "hbm_bytes_per_launch": round(hbm), "counters": res}
+    with open(PMC_FILE, "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+    print(json.dumps(rec))
+
+
 def main():
     args = parse()
+    if args.ingest_counters:
+        ingest_counters(*args.ingest_counters)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the simulator step shards by whole worlds with "
               "no exchange between GPUs, and this build measures one GPU's share (--gpus 1).",
@@ -130,7 +182,7 @@ def main():
     if os.path.exists(PMC_FILE):
         pm = json.load(open(PMC_FILE))
         if pm.get("source_digest") == source_digest("gd_step.hip", "gd_internal.h") and \
-                pm.get("workload") == "cfg1":
+                pm.get("workload") == WORKLOAD_TAG:
             traffic = pm["hbm_bytes_per_launch"]
     out = {
         "metric": "agent-steps/sec (full step) on 1 MI355X",
@@ -161,7 +213,7 @@ def main():
                  "active_agent_steps_per_s": round(value * vis_frac, 1)},
     }
     if args.copy_calibration:
-        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        a = torch.empty(COPY_ELEMS, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
         torch.cuda.synchronize()
         for _ in range(3):

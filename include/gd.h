@@ -76,6 +76,11 @@ typedef enum {
 #define GD_META_LAST (1 << 8)
 
 /* ---- limits --------------------------------------------------------------------------- */
+/* gd_config.obs_road */
+#define GD_ROAD_AUTO 0
+#define GD_ROAD_LDS 1
+#define GD_ROAD_GLOBAL 2
+
 #define GD_MAX_AGENTS_PER_WORLD 1024
 #define GD_MAX_ROAD_PER_WORLD (1 << 24)
 #define GD_MAX_TOP_K 960
@@ -97,16 +102,20 @@ typedef struct {
     float v_max;               /* speed clip (m/s) > 0 */
     float lidar_range;         /* LIDAR range (m) > 0 when lidar_rays > 0 */
     float collision_penalty;   /* reward -= penalty when the agent collided */
-    float cell_size;           /* road grid cell (m); 0 = library default (10 m) */
+    float cell_size;           /* road grid cell (m); 0 = library default (12 m) */
     int32_t obs_waves;         /* launch shape of the step kernel: waves per workgroup
                                   (1, 2, 4, 8, 12, 16; 0 = the shape with the most
                                   resident waves per compute unit that fits the LDS) */
     int32_t obs_bins;          /* distance bins of the top-K selection (64, 128, 256,
-                                  512; 0 = default) */
+                                  512, 1024; 0 = default) */
     int32_t obs_cands;         /* candidate-list entries per wave of the top-K selection
                                   (128, 256, 384, 512, 768, 1024; 0 = chosen with
                                   obs_waves; agents with more candidates rescan the grid) */
-    int32_t reserved[2];       /* must be zero */
+    int32_t obs_road;          /* where the step kernel reads a world's road points:
+                                  GD_ROAD_AUTO, GD_ROAD_LDS (staged in LDS for the whole
+                                  step; needs room for 16 B per point) or GD_ROAD_GLOBAL
+                                  (from the workspace through the caches) */
+    int32_t reserved;          /* must be zero */
 } gd_config;
 
 typedef struct {

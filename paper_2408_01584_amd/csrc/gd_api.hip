@@ -128,12 +128,14 @@ static gd_status check_config(const gd_config *c, const int32_t *h_agent_off,
           c->obs_waves == 8 || c->obs_waves == 12 || c->obs_waves == 16))
         return fail(GD_E_ARG, "obs_waves must be 0, 1, 2, 4, 8, 12 or 16");
     if (!(c->obs_bins == 0 || c->obs_bins == 64 || c->obs_bins == 128 || c->obs_bins == 256 ||
-          c->obs_bins == 512))
-        return fail(GD_E_ARG, "obs_bins must be 0, 64, 128, 256 or 512");
+          c->obs_bins == 512 || c->obs_bins == 1024))
+        return fail(GD_E_ARG, "obs_bins must be 0, 64, 128, 256, 512 or 1024");
     if (!(c->obs_cands == 0 || c->obs_cands == 128 || c->obs_cands == 256 || c->obs_cands == 384 ||
           c->obs_cands == 512 || c->obs_cands == 768 || c->obs_cands == 1024))
         return fail(GD_E_ARG, "obs_cands must be 0, 128, 256, 384, 512, 768 or 1024");
-    if (c->reserved[0] || c->reserved[1]) return fail(GD_E_ARG, "reserved fields must be zero");
+    if (!(c->obs_road == GD_ROAD_AUTO || c->obs_road == GD_ROAD_LDS || c->obs_road == GD_ROAD_GLOBAL))
+        return fail(GD_E_ARG, "obs_road must be GD_ROAD_AUTO, GD_ROAD_LDS or GD_ROAD_GLOBAL");
+    if (c->reserved) return fail(GD_E_ARG, "reserved field must be zero");
     const int W = c->num_worlds;
     if (h_agent_off[0] != 0 || h_road_off[0] != 0) return fail(GD_E_ARG, "offsets must start at 0");
     for (int w = 0; w < W; w++) {
@@ -157,53 +159,55 @@ static long long partner_slots_of(const gd_config *c, const int32_t *h_agent_off
     return s;
 }
 
-// Launch shape of the fused step: waves per workgroup, distance bins, LDS staging of the
-// road and size of the per-wave candidate list.  Among the shapes that fit, the one with
-// the most resident waves per compute unit wins (workgroups per CU by LDS, at most 24
-// waves per CU by registers), then the larger candidate list; explicit values in the
-// configuration restrict the search.
+// Launch shape of the step kernel: waves per workgroup, distance bins, candidate-list
+// entries per wave, and whether the road is staged in LDS.  Fields the config fixes are
+// kept; the rest maximise resident waves per compute unit (counting only the workgroups
+// the batch can fill), then prefer 512 bins, a candidate list of at least 512 entries
+// (the smallest such), and staged edge segments.  GD_ROAD_AUTO reads the road through the
+// caches, which leaves the LDS to larger per-wave buffers; GD_ROAD_LDS stages it.
 static bool launch_shape(const gd_config *c, int max_road, int max_cells, int max_edges,
                          int max_agents, int &waves, int &bins, int &road_cap, int &edge_cap,
-                         int &cand_cap) {
-    bins = c->obs_bins ? c->obs_bins : 256;
+                         int &cand_cap, int &idx16) {
     const int K = c->top_k;
+    idx16 = max_road < 65536 ? 1 : 0;
     const int agent_cap = std::max(max_agents, 1);
     const int cell_cap4 = (max_cells + 1 + 3) / 4 * 4;
+    const int wgs_needed = std::max(1, (c->num_worlds + 255) / 256);
     const int wave_opts[] = {16, 12, 8, 4, 2, 1};
     const int cand_opts[] = {1024, 768, 512, 384, 256, 128};
-    for (int staged = 1; staged >= 0; staged--) {
-        if (staged && K == 0) continue;
-        const int rc = staged ? std::max(max_road, 1) : 0;
-        if (staged && rc > 60000) continue;
-        int best_res = 0, best_w = 0, best_c = 0, best_e = 0;
-        for (int ec : {max_edges, 0}) {
-            for (int wv : wave_opts) {
-                if (c->obs_waves && wv != c->obs_waves) continue;
+    const int bin_opts[] = {512, 1024, 256, 128, 64};
+    auto bin_pref = [](int b) { return b == 512 ? 5 : b == 1024 ? 4 : b == 256 ? 3 : b == 128 ? 2 : 1; };
+    auto cand_pref = [](int cc) { return cc == 512 ? 3 : cc == 768 ? 2 : cc == 1024 ? 1 : 0; };
+    const bool staged = c->obs_road == GD_ROAD_LDS && K > 0;
+    if (staged && (max_road > 60000 || !idx16)) return false;
+    // a multiple of 4 points keeps the LDS regions after the road 16-byte aligned
+    const int rc = staged ? (std::max(max_road, 1) + 3) / 4 * 4 : 0;
+    long best = -1;
+    for (int ec : {max_edges, 0}) {
+        for (int wv : wave_opts) {
+            if (c->obs_waves && wv != c->obs_waves) continue;
+            for (int nb : bin_opts) {
+                if (c->obs_bins && nb != c->obs_bins) continue;
                 for (int cc : cand_opts) {
                     if (c->obs_cands && cc != c->obs_cands) continue;
-                    const size_t lds = step_lds_bytes(wv, bins, K, K ? cc : 0, rc, cell_cap4, ec, agent_cap);
+                    const size_t lds = step_lds_bytes(wv, nb, K, K ? cc : 0, rc, cell_cap4, ec,
+                                                      agent_cap, idx16 != 0);
                     if (lds > (size_t)kLdsBytes) continue;
-                    const int per_cu = std::min((int)((size_t)kLdsBytes / lds) * wv, 24);
-                    // prefer resident waves, then staged edges, then candidate capacity
-                    const int score = per_cu * 8 + (ec ? 4 : 0) + (cc >= 768 ? 2 : 0) + (cc >= 512 ? 1 : 0);
-                    if (score > best_res) {
-                        best_res = score;
-                        best_w = wv;
-                        best_c = cc;
-                        best_e = ec;
+                    const int wgs = std::min({(int)((size_t)kLdsBytes / lds), 32 / wv, wgs_needed});
+                    const long score = (long)wgs * wv * 1000 + bin_pref(nb) * 20 + cand_pref(cc) * 4 + (ec ? 1 : 0);
+                    if (score > best) {
+                        best = score;
+                        waves = wv;
+                        bins = nb;
+                        cand_cap = K ? cc : 0;
+                        edge_cap = ec;
                     }
                 }
             }
         }
-        if (best_w) {
-            waves = best_w;
-            cand_cap = K ? best_c : 0;
-            road_cap = rc;
-            edge_cap = best_e;
-            return true;
-        }
     }
-    return false;
+    road_cap = rc;
+    return best >= 0;
 }
 
 // workgroup order: costliest worlds first, so that the in-order dispatch of workgroups
@@ -476,9 +480,9 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
             max_cells = std::max(max_cells, g.nx * g.ny);
             max_edges = std::max(max_edges, g.n_edge);
         }
-        int waves = 0, bins = 0, road_cap = 0, edge_cap = 0, cand_cap = 0;
+        int waves = 0, bins = 0, road_cap = 0, edge_cap = 0, cand_cap = 0, idx16 = 0;
         if (!launch_shape(cfg, max_road, max_cells, max_edges, max_agents, waves, bins, road_cap,
-                          edge_cap, cand_cap)) {
+                          edge_cap, cand_cap, idx16)) {
             delete sim;
             return fail(GD_E_SIZE, "no launch shape fits the LDS (top_k %d, %d agents per world)",
                         cfg->top_k, max_agents);
@@ -486,6 +490,7 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
         sim->waves = waves;
         sim->bins = bins;
         sim->ctl.road_cap = road_cap;
+        sim->ctl.idx16 = idx16;
         sim->ctl.cell_cap4 = (max_cells + 1 + 3) / 4 * 4;
         sim->ctl.edge_cap = edge_cap;
         sim->ctl.cand_cap = cand_cap;

@@ -13,7 +13,7 @@ constexpr int kWave = 64;
 constexpr int kGridAxis = GD_GRID_MAX_CELLS_PER_AXIS;        // cells per axis, at most
 constexpr int kGridCells = kGridAxis * kGridAxis;            // cells per world, at most
 constexpr int kCellStride = kGridCells + 1;                  // CSR row length per world
-constexpr float kDefaultCell = 10.0f;
+constexpr float kDefaultCell = 12.0f;
 
 // Per-world uniform grid over the road points (and, separately, over the road-edge
 // segments keyed by their first endpoint).  Built once by gd_create.
@@ -73,6 +73,8 @@ struct StepCtl {
     const uint8_t *mask;       // [W] worlds to reset (kModeReset; NULL = all)
     const int *order;          // [W] world of each workgroup (longest first), NULL = identity
     int road_cap;              // road points staged in LDS per world (0 = read from global)
+    int idx16;                 // 1: every world has fewer than 65536 road points, so point
+                               // indices in LDS take 16 bits
     int cell_cap4;             // LDS slots for a world's grid cell starts (max cells + 1,
                                // rounded up to a multiple of 4)
     int edge_cap;              // edge segments staged in LDS per world (0 = read from global)
@@ -91,7 +93,7 @@ Layout make_layout(int W, long long A, long long R);
 hipError_t launch_build_grid(const SimArgs &a, float cell_size, hipStream_t s);
 hipError_t launch_step(const SimArgs &a, const StepCtl &c, int waves, int bins, hipStream_t s);
 size_t step_lds_bytes(int waves, int NB, int K, int ccap, int road_cap, int cell_cap4,
-                      int edge_cap, int agent_cap);
+                      int edge_cap, int agent_cap, bool idx16);
 
 // ---------------------------------------------------------------- device helpers
 

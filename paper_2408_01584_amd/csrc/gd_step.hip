@@ -129,32 +129,69 @@ __device__ __forceinline__ int lane_prefix(unsigned long long mask) {
                                      __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
 }
 
+// A value every lane of the wave holds (read from one LDS address by all lanes): moving it
+// to a scalar register lets the compiler treat what depends on it as wave-uniform, so that
+// loops bounded by it run as scalar loops instead of divergent ones.
+__device__ __forceinline__ float wave_uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Inclusive prefix sum over the 64 lanes with DPP moves: shifts by 1, 2, 4, 8 inside each
+// row of 16 lanes, then the last lane of row 0 (2) added to row 1 (3), then lane 31 added
+// to rows 2 and 3.  Lanes whose DPP source is out of range or whose row is masked add 0.
+__device__ __forceinline__ int wave_incl_scan(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return v;
+}
+
 __host__ __device__ inline int stage_cap(int K) { return ((K + 64 + 63) / 64) * 64; }
 
-// per-wave LDS: histogram NB ints | candidate list ccap indices | staging scap indices |
-// perm K ushorts.  Indices are 16-bit when the road is staged in LDS (a staged world has
-// far fewer than 65536 points), 32-bit otherwise.
-__host__ __device__ inline size_t wave_lds_bytes(int NB, int K, int ccap, int idx_bytes) {
-    size_t b = (size_t)NB * 4 + (size_t)ccap * idx_bytes + (size_t)stage_cap(K) * idx_bytes +
-               (size_t)K * 2;
+// Point indices and packed (bin, point) candidates: 16-bit / 32-bit when every world has
+// fewer than 65536 road points, 32-bit / 64-bit otherwise.
+template <bool IDX16>
+struct PointIndex {
+    using idx_t = int;
+    using cand_t = unsigned long long;
+    static constexpr int kShift = 32;
+};
+template <>
+struct PointIndex<true> {
+    using idx_t = unsigned short;
+    using cand_t = unsigned;
+    static constexpr int kShift = 16;
+};
+
+// per-wave LDS of phase 5:
+//   hist  NB ints        histogram of bin(d2), then the first (later: end) slot of each bin
+//   cand  ccap entries   (bin, point) of every point within the radius
+//   skey  scap floats    keys of the staged points (bins up to the cut bin)
+//   sq    scap indices   their points
+//   perm  K indices      point of each output slot
+__host__ __device__ inline size_t wave_lds_bytes(int NB, int K, int ccap, bool idx16) {
+    const size_t ib = idx16 ? 2 : 4, cb = idx16 ? 4 : 8;
+    const size_t b = (size_t)NB * 4 + (size_t)ccap * cb + (size_t)stage_cap(K) * (4 + ib) +
+                     (size_t)K * ib;
     return (b + 15) / 16 * 16;
 }
 
-template <bool STAGED>
-struct LdsIndex {
-    using type = int;
-};
-template <>
-struct LdsIndex<true> {
-    using type = unsigned short;
-};
-
 constexpr int kAgentArrays = 12;  // x y yaw v L W cos sin goal_x goal_y flags coll
 
-template <int NB, bool STAGED>
+// Road modes of the step kernel: where phase 5 reads the road, and the index width.
+enum RoadMode { kRoadGlobal32 = 0, kRoadGlobal16 = 1, kRoadLds = 2 };
+
+template <int NB, int RM>
 __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     extern __shared__ __align__(16) unsigned char smem[];
-    using idx_t = typename LdsIndex<STAGED>::type;
+    constexpr bool STAGED = RM == kRoadLds;
+    constexpr bool IDX16 = RM != kRoadGlobal32;
+    using idx_t = typename PointIndex<IDX16>::idx_t;
+    using cand_t = typename PointIndex<IDX16>::cand_t;
     constexpr int BPL = NB / kWave;  // bins per lane
     const int w = c.order ? c.order[blockIdx.x] : (int)blockIdx.x;
     const int tid = threadIdx.x;
@@ -172,59 +209,117 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     const int S = a.P >= 0 ? a.P : (n > 0 ? n - 1 : 0);
     const int mode = c.mode;
 
-    // LDS: [road xy][road dir/index][cell starts] (staged worlds)
-    //      [edge segments][edge cell starts] (when they fit) [agents] [per-wave buffers]
+    // LDS: [road xy][road dir/index][road cell starts] (staged worlds) [agents], then
+    //      either the edge segments with their cell starts (phases 0-2) or the per-wave
+    //      buffers (phase 5): the two are never live together.  Phase 5 reads nothing
+    //      from global memory when the road is staged: a global load issued after a
+    //      wave's observation stores waits for those stores to complete.
     float2 *sroad = reinterpret_cast<float2 *>(smem);
     float2 *saux = sroad + (STAGED ? c.road_cap : 0);
     int *scells = reinterpret_cast<int *>(saux + (STAGED ? c.road_cap : 0));
-    float4 *sedge = reinterpret_cast<float4 *>(scells + (STAGED ? c.cell_cap4 : 0));
-    int *secells = reinterpret_cast<int *>(sedge + c.edge_cap);
-    float *sag = reinterpret_cast<float *>(secells + (c.edge_cap ? c.cell_cap4 : 0));
+    float *sag = reinterpret_cast<float *>(scells + (STAGED ? c.cell_cap4 : 0));
     const int ac = c.agent_cap;
     float *sx = sag, *sy = sag + ac, *syaw = sag + 2 * ac, *sv = sag + 3 * ac;
     float *sL = sag + 4 * ac, *sW = sag + 5 * ac, *sc = sag + 6 * ac, *ss = sag + 7 * ac;
     float *sgx = sag + 8 * ac, *sgy = sag + 9 * ac;
     int *sf = reinterpret_cast<int *>(sag + 10 * ac);
     int *scoll = reinterpret_cast<int *>(sag + 11 * ac);
-    unsigned char *mine = reinterpret_cast<unsigned char *>(sag + kAgentArrays * ac) +
-                          (size_t)wid * wave_lds_bytes(NB, K, ccap, (int)sizeof(idx_t));
+    unsigned char *uni = reinterpret_cast<unsigned char *>(sag + kAgentArrays * ac);
+    float4 *sedge = reinterpret_cast<float4 *>(uni);
+    int *secells = reinterpret_cast<int *>(sedge + c.edge_cap);
+    unsigned char *mine = uni + (size_t)wid * wave_lds_bytes(NB, K, ccap, IDX16);
     int *hist = reinterpret_cast<int *>(mine);
-    idx_t *cand = reinterpret_cast<idx_t *>(hist + NB);
-    idx_t *stage = cand + ccap;
-    unsigned short *perm = reinterpret_cast<unsigned short *>(stage + scap);
+    cand_t *cand = reinterpret_cast<cand_t *>(hist + NB);
+    float *skey = reinterpret_cast<float *>(cand + ccap);
+    idx_t *sq = reinterpret_cast<idx_t *>(skey + scap);
+    idx_t *perm = sq + scap;
 
     const WorldGrid g = a.grid[w];
     const int ncell = g.nx * g.ny;
+    // phases 0 and 1 share one memory round trip: each thread issues the loads of its
+    // first agent and of its share of the staging copies before its first LDS store
+    int t = a.t[w];
+    struct AgentIn {
+        uint8_t f;
+        float x, y, yaw, v, L, W, gx, gy;
+        float2 act;
+    };
+    auto load_agent = [&](int i) {
+        const int gi = a0 + i;
+        AgentIn in;
+        in.f = a.fl[gi];
+        in.x = a.x[gi];
+        in.y = a.y[gi];
+        in.yaw = a.yaw[gi];
+        in.v = a.v[gi];
+        in.L = a.len[gi];
+        in.W = a.wid[gi];
+        in.gx = a.gx[gi];
+        in.gy = a.gy[gi];
+        // the action is read for every agent (no dependence on the flags load)
+        in.act = mode == kModeStep ? c.actions[gi] : make_float2(0.f, 0.f);
+        return in;
+    };
+    // (an in-bounds agent for every thread, so that no branch holds the loads back)
+    AgentIn first{};
+    if (a.A > 0) first = load_agent(min(tid, n - 1) < 0 ? -a0 : min(tid, n - 1));
+
     // phase 0: the world's cell-sorted road points and grid rows into LDS (phase 5), and
     // its edge segments with their grid rows (phase 2b) when they fit
-    if (STAGED && K > 0) {
-        for (int k = tid; k < nr; k += bs) {
-            sroad[k] = a.pt_xy[r0 + k];
-            saux[k] = a.pt_aux[r0 + k];
-        }
-        const int *cs0 = a.cell_start + (size_t)w * kCellStride;
-        for (int k = tid; k <= ncell; k += bs) scells[k] = cs0[k];
-    }
-    if (c.edge_cap && mode == kModeStep) {
-        for (int k = tid; k < g.n_edge; k += bs) sedge[k] = a.eseg[r0 + k];
-        const int *ec0 = a.ecell_start + (size_t)w * kCellStride;
-        for (int k = tid; k <= ncell; k += bs) secells[k] = ec0[k];
+    {
+        const int nrd = (STAGED && K > 0) ? nr : 0;
+        const int nrc = (STAGED && K > 0) ? ncell + 1 : 0;
+        const int ned = (c.edge_cap && mode == kModeStep) ? g.n_edge : 0;
+        const int nec = (c.edge_cap && mode == kModeStep) ? ncell + 1 : 0;
+        const float2 *rsrc = a.pt_xy + r0;
+        const float2 *asrc = a.pt_aux + r0;
+        const int *csrc = a.cell_start + (size_t)w * kCellStride;
+        const float4 *esrc = a.eseg + r0;
+        const int *ecsrc = a.ecell_start + (size_t)w * kCellStride;
+        const int most = max(max(nrd, nrc), max(ned, nec));
+        constexpr int U = 4;
+        auto stage = [&](int b0) {
+            float2 rv[U], av[U];
+            int cv[U], ecv[U];
+            float4 ev[U];
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int k = b0 + u * bs + tid;
+                rv[u] = k < nrd ? rsrc[k] : make_float2(0.f, 0.f);
+                av[u] = k < nrd ? asrc[k] : make_float2(0.f, 0.f);
+                cv[u] = k < nrc ? csrc[k] : 0;
+                ev[u] = k < ned ? esrc[k] : make_float4(0.f, 0.f, 0.f, 0.f);
+                ecv[u] = k < nec ? ecsrc[k] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; u++) {
+                const int k = b0 + u * bs + tid;
+                if (k < nrd) {
+                    sroad[k] = rv[u];
+                    saux[k] = av[u];
+                }
+                if (k < nrc) scells[k] = cv[u];
+                if (k < ned) sedge[k] = ev[u];
+                if (k < nec) secells[k] = ecv[u];
+            }
+        };
+        // the first batch outside the loop, so that no loop entry waits for the agent loads
+        stage(0);
+        for (int b0 = U * bs; b0 < most; b0 += U * bs) stage(b0);
     }
 
     // phase 1: agents into LDS, dynamics of the alive ones
-    int t = a.t[w];
     {
         bool nonfinite = false;
         for (int i = tid; i < n; i += bs) {
             const int gi = a0 + i;
-            const int f = a.fl[gi];
-            float x = a.x[gi], y = a.y[gi], yaw = a.yaw[gi], v = a.v[gi];
-            const float L = a.len[gi];
-            // the action is read for every agent (no dependence on the flags load)
-            const float2 act = mode == kModeStep ? c.actions[gi] : make_float2(0.f, 0.f);
+            const AgentIn in = i == tid ? first : load_agent(i);
+            const int f = in.f;
+            float x = in.x, y = in.y, yaw = in.yaw, v = in.v;
+            const float L = in.L;
             if (mode == kModeStep && (f & GD_FLAG_ALIVE)) {
-                if (!(isfinite(act.x) && isfinite(act.y))) nonfinite = true;
-                bicycle(x, y, yaw, v, L, act.x, act.y, a.dt, a.vmax);
+                if (!(isfinite(in.act.x) && isfinite(in.act.y))) nonfinite = true;
+                bicycle(x, y, yaw, v, L, in.act.x, in.act.y, a.dt, a.vmax);
                 a.x[gi] = x;
                 a.y[gi] = y;
                 a.yaw[gi] = yaw;
@@ -235,9 +330,9 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             syaw[i] = yaw;
             sv[i] = v;
             sL[i] = L;
-            sW[i] = a.wid[gi];
-            sgx[i] = a.gx[gi];
-            sgy[i] = a.gy[gi];
+            sW[i] = in.W;
+            sgx[i] = in.gx;
+            sgy[i] = in.gy;
             float sn, cs;
             sincosf(yaw, &sn, &cs);
             sc[i] = cs;
@@ -251,29 +346,29 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
 
     bool do_reset = false, keep_outcome = false;
     if (mode == kModeStep) {
-        // phase 2a: all agent pairs of the world over the whole workgroup
-        const int npairs = n * n;
-        for (int e = tid; e < npairs; e += bs) {
-            const int i = e / n;
-            const int j = e - i * n;
-            if (i == j || !(sf[i] & GD_FLAG_ALIVE) || !(sf[j] & GD_FLAG_ALIVE)) continue;
-            const float dx = sx[j] - sx[i], dy = sy[j] - sy[i];
-            const float rr = 0.5f * (sqrtf(sL[i] * sL[i] + sW[i] * sW[i]) +
-                                     sqrtf(sL[j] * sL[j] + sW[j] * sW[j])) + 1e-3f;
-            if (dx * dx + dy * dy > rr * rr) continue;
-            if (sat_box_box(dx, dy, sc[i], ss[i], sL[i], sW[i], sc[j], ss[j], sL[j], sW[j]) < 0.0f)
-                atomicOr(&scoll[i], (int)GD_FLAG_COLL_AGENT);
-        }
-        // phase 2b: road edges, one wave per agent, lanes over the segments keyed in the
-        // grid cells under the box (segments are keyed by their first point: widen by the
-        // longest segment)
+        // phase 2: collisions, one wave per alive agent i: lanes over the other agents
+        // (oriented boxes), then lanes over the edge segments keyed in the grid cells under
+        // the box (segments are keyed by their first point: widen by the longest segment)
         {
             const int *ecs = c.edge_cap ? secells : a.ecell_start + (size_t)w * kCellStride;
             const float4 *es = c.edge_cap ? sedge : a.eseg + r0;
             for (int i = wid; i < n; i += nwaves) {
-                if (!(sf[i] & GD_FLAG_ALIVE)) continue;
-                const float xi = sx[i], yi = sy[i], ci = sc[i], si = ss[i];
-                const float hL = 0.5f * sL[i], hW = 0.5f * sW[i];
+                if (!(wave_uniform(sf[i]) & GD_FLAG_ALIVE)) continue;
+                const float xi = wave_uniform(sx[i]), yi = wave_uniform(sy[i]);
+                const float ci = wave_uniform(sc[i]), si = wave_uniform(ss[i]);
+                const float Li = wave_uniform(sL[i]), Wi = wave_uniform(sW[i]);
+                const float di = sqrtf(Li * Li + Wi * Wi);
+                bool ha = false;
+                for (int j = lane; j < n; j += kWave) {
+                    if (j == i || !(sf[j] & GD_FLAG_ALIVE)) continue;
+                    const float dx = sx[j] - xi, dy = sy[j] - yi;
+                    const float rr = 0.5f * (di + sqrtf(sL[j] * sL[j] + sW[j] * sW[j])) + 1e-3f;
+                    if (dx * dx + dy * dy > rr * rr) continue;
+                    if (sat_box_box(dx, dy, ci, si, Li, Wi, sc[j], ss[j], sL[j], sW[j]) < 0.0f) ha = true;
+                }
+                const bool agent_hit = __ballot(ha) != 0ull;
+
+                const float hL = 0.5f * Li, hW = 0.5f * Wi;
                 const float ex = fabsf(ci) * hL + fabsf(si) * hW;
                 const float ey = fabsf(si) * hL + fabsf(ci) * hW;
                 const float m = g.max_seg + 1e-3f;
@@ -297,7 +392,8 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
                         hit = __ballot(h) != 0ull;
                     }
                 }
-                if (hit && lane == 0) atomicOr(&scoll[i], (int)GD_FLAG_COLL_EDGE);
+                if (lane == 0)
+                    scoll[i] = (agent_hit ? (int)GD_FLAG_COLL_AGENT : 0) | (hit ? (int)GD_FLAG_COLL_EDGE : 0);
             }
         }
         __syncthreads();
@@ -394,20 +490,24 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
 
     // phase 5: partners and road top-K, one wave per agent
     const float2 *rxy = STAGED ? sroad : (a.pt_xy + r0);
-    const float2 *aux = STAGED ? saux : (a.pt_aux + r0);
+    const float2 *aux = STAGED ? saux : (a.pt_aux + r0);  // (direction, local index | type << 24)
     const int *cst = STAGED ? scells : (a.cell_start + (size_t)w * kCellStride);
     const float R = a.R_obs, R2 = a.R2_obs;
     const float bscale = (float)NB / R2;
     const float marg = 1e-3f * g.cs + 1e-3f;
+    constexpr int SH = PointIndex<IDX16>::kShift;
+    const cand_t qmask = (cand_t)((1ull << SH) - 1);
 
+    const long long pbase_w = a.P >= 0 ? 0 : a.pbase[w];
     for (int l = wid; l < n; l += nwaves) {
         const int ai = a0 + l;
-        const bool vis = (sf[l] & GD_FLAG_VISIBLE) != 0;
-        const float px = sx[l], py = sy[l], yaw = syaw[l], csy = sc[l], sny = ss[l];
+        const bool vis = (wave_uniform(sf[l]) & GD_FLAG_VISIBLE) != 0;
+        const float px = wave_uniform(sx[l]), py = wave_uniform(sy[l]), yaw = wave_uniform(syaw[l]);
+        const float csy = wave_uniform(sc[l]), sny = wave_uniform(ss[l]);
 
         // ---- partners: lane = slot; slot s holds the s-th other agent in index order
         if (S > 0) {
-            const long long base = a.P >= 0 ? (long long)ai * a.P : a.pbase[w] + (long long)l * S;
+            const long long base = a.P >= 0 ? (long long)ai * a.P : pbase_w + (long long)l * S;
             for (int s = lane; s < S; s += kWave) {
                 const int j = s < l ? s : s + 1;
                 float f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f, f4 = 0.f, f5 = 0.f;
@@ -441,43 +541,75 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             continue;
         }
         for (int b = lane; b < NB; b += kWave) hist[b] = 0;
-        // a. candidate rows, one per lane (at most 64 rows per world)
+        // a. candidate rows: lane r holds the span [q0, q1) of grid row rlo + r and its
+        //    place [end - len, end) in the concatenation of all the spans
         const int rlo = cell_coord(py - R, g.oy, g.inv_cs, g.ny);
         const int rhi = cell_coord(py + R, g.oy, g.inv_cs, g.ny);
-        const int nrows = rhi - rlo + 1;
-        int sq0 = 0, sq1 = 0;
-        if (lane < nrows) row_span(g, cst, rlo + lane, px, py, R, marg, sq0, sq1);
-        wave_sync();
+        const int nrows = rhi - rlo + 1;  // at most kGridAxis
+        int q0 = 0, q1 = 0;
+        if (lane < nrows) row_span(g, cst, rlo + lane, px, py, R, marg, q0, q1);
+        const int len = q1 - q0;
+        const int end = wave_incl_scan(len);
+        const int M = __builtin_amdgcn_readlane(end, kWave - 1);
+        const int off = end - len;
+        const int delta = q0 - off;  // point = position + delta inside the row
 
-        // b. one scan: candidate list + histogram of bin(d2); two chunks of 64 points per
-        //    iteration so that both LDS loads are in flight together
+        // b. one pass over the concatenated spans, four chunks of 64 positions at a time
+        //    (their LDS loads in flight together): the key of each point; points within
+        //    the radius count in the histogram of bins (LDS atomics, nothing waits on
+        //    them) and go to the candidate list with their bin
         int ncand = 0;
-        for (int rr = 0; rr < nrows; rr++) {
-            const int q0 = __builtin_amdgcn_readlane(sq0, rr);
-            const int q1 = __builtin_amdgcn_readlane(sq1, rr);
-            for (int base = q0; base < q1; base += 2 * kWave) {
-                const int qa = base + lane, qb = base + kWave + lane;
-                const float2 pa = rxy[min(qa, q1 - 1)];
-                const float2 pb = rxy[min(qb, q1 - 1)];
-                const float ka = key32(px, py, pa.x, pa.y);
-                const float kb = key32(px, py, pb.x, pb.y);
-                const bool ina = qa < q1 && ka <= R2;
-                const bool inb = qb < q1 && kb <= R2;
-                if (ina) atomicAdd(&hist[bin_of(ka, bscale, NB)], 1);
-                if (inb) atomicAdd(&hist[bin_of(kb, bscale, NB)], 1);
-                const unsigned long long bala = __ballot(ina);
-                const unsigned long long balb = __ballot(inb);
-                const int posa = ncand + lane_prefix(bala);
-                const int na = __popcll(bala);
-                const int posb = ncand + na + lane_prefix(balb);
-                if (ina && posa < ccap) cand[posa] = (idx_t)qa;
-                if (inb && posb < ccap) cand[posb] = (idx_t)qb;
-                ncand += na + __popcll(balb);
+        int r = 0;  // the first row that ends after the current chunk's start
+        // point of this lane's position in the chunk starting at b (< M): the row that
+        // holds position b, then the later rows that start inside the chunk
+        auto chunk_point = [&](int b) {
+            while (__builtin_amdgcn_readlane(end, r) <= b) r++;
+            const int p = b + lane;
+            int q = p + __builtin_amdgcn_readlane(delta, r);
+            for (int rr = r + 1; rr < nrows; rr++) {
+                const int o = __builtin_amdgcn_readlane(off, rr);
+                if (o >= b + kWave) break;
+                const int d = __builtin_amdgcn_readlane(delta, rr);
+                q = p >= o ? p + d : q;
+            }
+            return q;
+        };
+        constexpr int SU = 4;
+        for (int base = 0; base < M; base += SU * kWave) {
+            int qv[SU];
+            float2 pt[SU];
+#pragma unroll
+            for (int u = 0; u < SU; u++) qv[u] = base + u * kWave < M ? chunk_point(base + u * kWave) : 0;
+#pragma unroll
+            for (int u = 0; u < SU; u++) pt[u] = rxy[base + u * kWave + lane < M ? qv[u] : 0];
+#pragma unroll
+            for (int u = 0; u < SU; u++) {
+                const float k = key32(px, py, pt[u].x, pt[u].y);
+                const bool in = base + u * kWave + lane < M && k <= R2;
+                const int bn = bin_of(k, bscale, NB);
+                if (in) atomicAdd(&hist[bn], 1);
+                const unsigned long long bal = __ballot(in);
+                const int pos = ncand + lane_prefix(bal);
+                if (in && pos < ccap) cand[pos] = ((cand_t)bn << SH) | (cand_t)qv[u];
+                ncand += __popcll(bal);
             }
         }
+        const bool listed = ncand <= ccap;
+        // points within the radius row by row (when the list overflowed)
+        auto each_in_radius = [&](auto &&f) {
+            for (int rr = 0; rr < nrows; rr++) {
+                const int b0 = __builtin_amdgcn_readlane(q0, rr);
+                const int b1 = __builtin_amdgcn_readlane(q1, rr);
+                for (int qq = b0 + lane; qq < b1; qq += kWave) {
+                    const float2 pt = rxy[qq];
+                    const float k = key32(px, py, pt.x, pt.y);
+                    if (k <= R2) f(qq, k);
+                }
+            }
+        };
         wave_sync();
 
-        // c. prefix scan: hist[b] <- first slot of bin b
+        // c. prefix scan: hist[b] <- first slot of bin b; the bin holding the K-th key
         int cnt[BPL];
         int run = 0;
 #pragma unroll
@@ -485,13 +617,8 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             cnt[j] = hist[lane * BPL + j];
             run += cnt[j];
         }
-        int inc = run;
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const int o = __shfl_up(inc, d, kWave);
-            if (lane >= d) inc += o;
-        }
-        const int total = __shfl(inc, kWave - 1, kWave);
+        const int inc = wave_incl_scan(run);
+        const int total = __builtin_amdgcn_readlane(inc, kWave - 1);
         {
             int st = inc - run;
 #pragma unroll
@@ -515,67 +642,84 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             }
             const unsigned long long bal = __ballot(mine_b >= 0);
             const int src = __ffsll((long long)bal) - 1;
-            bstar = __shfl(mine_b, src, kWave);
-            need = __shfl(mine_end, src, kWave);
+            bstar = __builtin_amdgcn_readlane(mine_b, src);
+            need = __builtin_amdgcn_readlane(mine_end, src);
         }
         wave_sync();
         const int cut_start = hist[bstar];
         const bool overflow = need > scap;
 
-        // d. scatter the candidates of bins <= bstar, bin by bin (hist[b] becomes the end
-        //    of bin b, i.e. the start of bin b + 1, for every staged bin)
-        if (total <= ccap) {
-            for (int ci = lane; ci < total; ci += kWave) {
-                const int q = cand[ci];
-                const float2 p = rxy[q];
-                const float k = key32(px, py, p.x, p.y);
-                const int b = bin_of(k, bscale, NB);
-                if (b < bstar || (b == bstar && !overflow)) stage[atomicAdd(&hist[b], 1)] = (idx_t)q;
-            }
-        } else {
-            for (int rr = 0; rr < nrows; rr++) {
-                const int q0 = __builtin_amdgcn_readlane(sq0, rr);
-                const int q1 = __builtin_amdgcn_readlane(sq1, rr);
-                for (int base = q0; base < q1; base += kWave) {
-                    const int q = base + lane;
-                    if (q < q1) {
-                        const float2 p = rxy[q];
-                        const float k = key32(px, py, p.x, p.y);
-                        if (k <= R2) {
-                            const int b = bin_of(k, bscale, NB);
-                            if (b < bstar || (b == bstar && !overflow))
-                                stage[atomicAdd(&hist[b], 1)] = (idx_t)q;
-                        }
+        // d. scatter the points of bins <= bstar bin by bin, with their keys (hist[b]
+        //    becomes the end of bin b, i.e. the start of bin b + 1, for every staged bin)
+        if (listed) {
+            for (int c0 = 0; c0 < ncand; c0 += SU * kWave) {
+                cand_t cv[SU];
+                int pos[SU], qs[SU];
+                float2 pt[SU];
+#pragma unroll
+                for (int u = 0; u < SU; u++) {
+                    const int ci = c0 + u * kWave + lane;
+                    cv[u] = cand[ci < ncand ? ci : 0];
+                }
+#pragma unroll
+                for (int u = 0; u < SU; u++) {
+                    const int ci = c0 + u * kWave + lane;
+                    const int b = (int)(cv[u] >> SH);
+                    qs[u] = (int)(cv[u] & qmask);
+                    pos[u] = scap;
+                    pt[u] = make_float2(0.f, 0.f);
+                    if (ci < ncand && (b < bstar || (b == bstar && !overflow))) {
+                        pt[u] = rxy[qs[u]];
+                        pos[u] = atomicAdd(&hist[b], 1);
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < SU; u++) {
+                    if (pos[u] < scap) {
+                        skey[pos[u]] = key32(px, py, pt[u].x, pt[u].y);
+                        sq[pos[u]] = (idx_t)qs[u];
                     }
                 }
             }
+        } else {
+            each_in_radius([&](int q, float k) {
+                const int b = bin_of(k, bscale, NB);
+                if (b < bstar || (b == bstar && !overflow)) {
+                    const int pos = atomicAdd(&hist[b], 1);
+                    if (pos < scap) {
+                        skey[pos] = k;
+                        sq[pos] = (idx_t)q;
+                    }
+                }
+            });
         }
         wave_sync();
 
-        // e. rank inside each bin by (d2, world-local index)
+        // e. rank inside each bin by (d2, world-local index): count the bin mates with a
+        //    smaller key (branch-free); exact key ties are ordered by index in a second
+        //    pass that only lanes with a tie take
         const int nstaged = overflow ? cut_start : need;
         for (int p = lane; p < nstaged; p += kWave) {
-            const int q = stage[p];
-            const float2 pp = rxy[q];
-            const unsigned kb = __float_as_uint(key32(px, py, pp.x, pp.y));
-            const int b = bin_of(__uint_as_float(kb), bscale, NB);
+            const float k = skey[p];
+            const int q = sq[p];
+            const int b = bin_of(k, bscale, NB);
             const int lo = b > 0 ? hist[b - 1] : 0;
             const int hi = hist[b];
             int rank = 0;
-            int my_idx = -1;
+            int tie = 0;
             for (int m = lo; m < hi; m++) {
-                const int qo = stage[m];
-                const float2 po = rxy[qo];
-                const unsigned ko = __float_as_uint(key32(px, py, po.x, po.y));
-                if (ko < kb) {
-                    rank++;
-                } else if (ko == kb && m != p) {
-                    if (my_idx < 0) my_idx = __float_as_int(aux[q].y) & 0xffffff;
-                    rank += (__float_as_int(aux[qo].y) & 0xffffff) < my_idx;
-                }
+                const float ko = skey[m];
+                rank += (int)(ko < k);
+                tie |= (int)(ko == k) & (int)(m != p);
+            }
+            if (tie) {
+                const int my_idx = __float_as_int(aux[q].y) & 0xffffff;
+                for (int m = lo; m < hi; m++)
+                    if (m != p && skey[m] == k)
+                        rank += (int)((__float_as_int(aux[sq[m]].y) & 0xffffff) < my_idx);
             }
             const int fin = lo + rank;
-            if (fin < K) perm[fin] = (unsigned short)p;
+            if (fin < K) perm[fin] = (idx_t)q;
         }
 
         if (overflow) {
@@ -584,23 +728,13 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             bool first = true;
             for (int s = cut_start; s < K; s++) {
                 unsigned long long best = ~0ull;
-                for (int rr = 0; rr < nrows; rr++) {
-                    const int q0 = __builtin_amdgcn_readlane(sq0, rr);
-                    const int q1 = __builtin_amdgcn_readlane(sq1, rr);
-                    for (int base = q0; base < q1; base += kWave) {
-                        const int q = base + lane;
-                        if (q < q1) {
-                            const float2 p = rxy[q];
-                            const float k = key32(px, py, p.x, p.y);
-                            if (k <= R2 && bin_of(k, bscale, NB) == bstar) {
-                                const unsigned idx = (unsigned)(__float_as_int(aux[q].y) & 0xffffff);
-                                const unsigned long long key =
-                                    ((unsigned long long)__float_as_uint(k) << 32) | idx;
-                                if ((first || key > prev) && key < best) best = key;
-                            }
-                        }
+                each_in_radius([&](int q, float k) {
+                    if (bin_of(k, bscale, NB) == bstar) {
+                        const unsigned idx = (unsigned)(__float_as_int(aux[q].y) & 0xffffff);
+                        const unsigned long long key = ((unsigned long long)__float_as_uint(k) << 32) | idx;
+                        if ((first || key > prev) && key < best) best = key;
                     }
-                }
+                });
                 best = wave_min_u64(best);
                 prev = best;
                 first = false;
@@ -616,21 +750,33 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
         }
         wave_sync();
 
-        // f. the K slots in order
+        // f. the K slots in order, four per lane at a time so that their point loads
+        //    are in flight together
         const int direct_end = overflow ? cut_start : nsel;
-        for (int s = lane; s < K; s += kWave) {
-            if (s < direct_end) {
-                const int q = stage[perm[s]];
-                const float2 p = rxy[q];
-                const float2 x2 = aux[q];
-                const int bits = __float_as_int(x2.y);
-                const float dx = p.x - px, dy = p.y - py;
-                out[s] = make_float4(csy * dx + sny * dy, -sny * dx + csy * dy, wrap_pi(x2.x - yaw),
-                                     (float)((unsigned)bits >> 24));
-                oidx[s] = bits & 0xffffff;
-            } else if (s >= nsel) {
-                out[s] = make_float4(0.f, 0.f, 0.f, 0.f);
-                oidx[s] = -1;
+        for (int s0 = 0; s0 < K; s0 += 4 * kWave) {
+            float2 pt[4], x2[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int s = s0 + u * kWave + lane;
+                if (s < direct_end) {
+                    const int q = min((int)perm[s], nr - 1);  // (a slot always holds a point)
+                    pt[u] = rxy[q];
+                    x2[u] = aux[q];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int s = s0 + u * kWave + lane;
+                if (s < direct_end) {
+                    const int bits = __float_as_int(x2[u].y);
+                    const float dx = pt[u].x - px, dy = pt[u].y - py;
+                    out[s] = make_float4(csy * dx + sny * dy, -sny * dx + csy * dy,
+                                         wrap_pi(x2[u].x - yaw), (float)((unsigned)bits >> 24));
+                    oidx[s] = bits & 0xffffff;
+                } else if (s >= nsel && s < K) {
+                    out[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    oidx[s] = -1;
+                }
             }
         }
         wave_sync();
@@ -638,20 +784,20 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
 }
 
 size_t step_lds_bytes(int waves, int NB, int K, int ccap, int road_cap, int cell_cap4,
-                      int edge_cap, int agent_cap) {
-    const int idx_bytes = road_cap > 0 ? 2 : 4;
-    const size_t staged = road_cap > 0 ? (size_t)road_cap * 16 + (size_t)cell_cap4 * 4 : 0;
+                      int edge_cap, int agent_cap, bool idx16) {
+    const bool staged = road_cap > 0;
+    const size_t road = staged ? (size_t)road_cap * 16 + (size_t)cell_cap4 * 4 : 0;
     const size_t edges = edge_cap > 0 ? (size_t)edge_cap * 16 + (size_t)cell_cap4 * 4 : 0;
-    return staged + edges + (size_t)agent_cap * 4 * kAgentArrays +
-           (size_t)waves * wave_lds_bytes(NB, K, ccap, idx_bytes);
+    const size_t per_wave = (size_t)waves * wave_lds_bytes(NB, K, ccap, idx16 || staged);
+    return road + (size_t)agent_cap * 4 * kAgentArrays + (edges > per_wave ? edges : per_wave);
 }
 
 // raise the kernel's dynamic-LDS limit to what this launch needs (once per size increase)
-template <int NB, bool STAGED>
+template <int NB, int RM>
 static hipError_t prepare(size_t lds) {
     static size_t allowed = 0;  // per instantiation
     if (lds > allowed) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_step<NB, STAGED>,
+        hipError_t e = hipFuncSetAttribute((const void *)k_step<NB, RM>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         allowed = lds;
@@ -659,21 +805,26 @@ static hipError_t prepare(size_t lds) {
     return hipSuccess;
 }
 
-template <int NB, bool STAGED>
+static size_t lds_of(const SimArgs &a, const StepCtl &c, int waves, int NB) {
+    return step_lds_bytes(waves, NB, a.K, c.cand_cap, c.road_cap, c.cell_cap4, c.edge_cap,
+                          c.agent_cap, c.idx16 != 0);
+}
+
+template <int NB, int RM>
 static hipError_t launch_one(const SimArgs &a, const StepCtl &c, int waves, hipStream_t st) {
-    const size_t lds = step_lds_bytes(waves, NB, a.K, c.cand_cap, c.road_cap, c.cell_cap4, c.edge_cap, c.agent_cap);
-    hipError_t e = prepare<NB, STAGED>(lds);
+    const size_t lds = lds_of(a, c, waves, NB);
+    hipError_t e = prepare<NB, RM>(lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_step<NB, STAGED>), dim3(a.W), dim3(waves * kWave), lds, st, a, c);
+    hipLaunchKernelGGL((k_step<NB, RM>), dim3(a.W), dim3(waves * kWave), lds, st, a, c);
     return hipGetLastError();
 }
 
-template <int NB, bool STAGED>
+template <int NB, int RM>
 static bool node_one(const SimArgs *a, const StepCtl *c, int waves, hipKernelNodeParams &p,
                      void **args) {
-    const size_t lds = step_lds_bytes(waves, NB, a->K, c->cand_cap, c->road_cap, c->cell_cap4, c->edge_cap, c->agent_cap);
-    if (prepare<NB, STAGED>(lds) != hipSuccess) return false;
-    p.func = (void *)k_step<NB, STAGED>;
+    const size_t lds = lds_of(*a, *c, waves, NB);
+    if (prepare<NB, RM>(lds) != hipSuccess) return false;
+    p.func = (void *)k_step<NB, RM>;
     p.gridDim = dim3(a->W);
     p.blockDim = dim3(waves * kWave);
     p.sharedMemBytes = (unsigned)lds;
@@ -684,21 +835,38 @@ static bool node_one(const SimArgs *a, const StepCtl *c, int waves, hipKernelNod
     return true;
 }
 
+static int road_mode(const StepCtl &c) {
+    return c.road_cap ? kRoadLds : (c.idx16 ? kRoadGlobal16 : kRoadGlobal32);
+}
+
+template <int NB>
+static bool node_nb(const SimArgs *a, const StepCtl *c, int waves, hipKernelNodeParams &p, void **args) {
+    switch (road_mode(*c)) {
+        case kRoadLds: return node_one<NB, kRoadLds>(a, c, waves, p, args);
+        case kRoadGlobal16: return node_one<NB, kRoadGlobal16>(a, c, waves, p, args);
+        default: return node_one<NB, kRoadGlobal32>(a, c, waves, p, args);
+    }
+}
+
 // kernel node of the fused step for graph mode (same kernel and shape as launch_step)
 bool step_kernel_node(const SimArgs *a, const StepCtl *c, int waves, int bins,
                       hipKernelNodeParams &p, void **args) {
-    const bool staged = c->road_cap != 0;
     switch (bins) {
-        case 64: return staged ? node_one<64, true>(a, c, waves, p, args) : node_one<64, false>(a, c, waves, p, args);
-        case 128: return staged ? node_one<128, true>(a, c, waves, p, args) : node_one<128, false>(a, c, waves, p, args);
-        case 512: return staged ? node_one<512, true>(a, c, waves, p, args) : node_one<512, false>(a, c, waves, p, args);
-        default: return staged ? node_one<256, true>(a, c, waves, p, args) : node_one<256, false>(a, c, waves, p, args);
+        case 64: return node_nb<64>(a, c, waves, p, args);
+        case 128: return node_nb<128>(a, c, waves, p, args);
+        case 512: return node_nb<512>(a, c, waves, p, args);
+        case 1024: return node_nb<1024>(a, c, waves, p, args);
+        default: return node_nb<256>(a, c, waves, p, args);
     }
 }
 
 template <int NB>
 static hipError_t launch_nb(const SimArgs &a, const StepCtl &c, int waves, hipStream_t st) {
-    return c.road_cap ? launch_one<NB, true>(a, c, waves, st) : launch_one<NB, false>(a, c, waves, st);
+    switch (road_mode(c)) {
+        case kRoadLds: return launch_one<NB, kRoadLds>(a, c, waves, st);
+        case kRoadGlobal16: return launch_one<NB, kRoadGlobal16>(a, c, waves, st);
+        default: return launch_one<NB, kRoadGlobal32>(a, c, waves, st);
+    }
 }
 
 hipError_t launch_step(const SimArgs &a, const StepCtl &c, int waves, int bins, hipStream_t st) {
@@ -707,6 +875,7 @@ hipError_t launch_step(const SimArgs &a, const StepCtl &c, int waves, int bins, 
         case 64: return launch_nb<64>(a, c, waves, st);
         case 128: return launch_nb<128>(a, c, waves, st);
         case 512: return launch_nb<512>(a, c, waves, st);
+        case 1024: return launch_nb<1024>(a, c, waves, st);
         default: return launch_nb<256>(a, c, waves, st);
     }
 }

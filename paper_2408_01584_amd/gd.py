@@ -22,6 +22,7 @@ GD_AUTO_RESET, GD_TERMINATE_ON_COLLISION, GD_CHECK_FINITE, GD_USE_GRAPH = 1, 2, 
 ENTRY_POINTS = ("gd_partner_slots", "gd_workspace_size", "gd_create", "gd_reset", "gd_step",
                 "gd_obs", "gd_rollout_fwd", "gd_rollout_bwd", "gd_set_obs_buffers", "gd_set_timing",
                 "gd_get_timing", "gd_check", "gd_destroy", "gd_last_error")
+GD_ROAD_AUTO, GD_ROAD_LDS, GD_ROAD_GLOBAL = 0, 1, 2
 GD_PHASE_STEP, GD_PHASE_LIDAR, GD_PHASE_ROLLOUT_FWD, GD_PHASE_ROLLOUT_BWD = range(4)
 GD_NUM_PHASES = 4
 
@@ -38,7 +39,7 @@ class gd_config(C.Structure):
                 ("dt", C.c_float), ("obs_radius", C.c_float), ("goal_radius", C.c_float),
                 ("v_max", C.c_float), ("lidar_range", C.c_float), ("collision_penalty", C.c_float),
                 ("cell_size", C.c_float), ("obs_waves", C.c_int32), ("obs_bins", C.c_int32),
-                ("obs_cands", C.c_int32), ("reserved", C.c_int32 * 2)]
+                ("obs_cands", C.c_int32), ("obs_road", C.c_int32), ("reserved", C.c_int32)]
 
 
 _BUF_FIELDS = ("agent_off", "road_off", "x", "y", "yaw", "speed", "length", "width", "goal_x",

@@ -16,7 +16,7 @@ from . import gd as G
 
 def config_from_params(p, num_worlds: int, graph: bool = False, check_finite: bool = False,
                        cell_size: float = 0.0, obs_waves: int = 0, obs_bins: int = 0,
-                       obs_cands: int = 0) -> G.gd_config:
+                       obs_cands: int = 0, obs_road: int = 0) -> G.gd_config:
     flags = (G.GD_AUTO_RESET if p.auto_reset else 0) | \
         (G.GD_TERMINATE_ON_COLLISION if p.terminate_on_collision else 0) | \
         (G.GD_CHECK_FINITE if check_finite else 0) | (G.GD_USE_GRAPH if graph else 0)
@@ -37,6 +37,7 @@ def config_from_params(p, num_worlds: int, graph: bool = False, check_finite: bo
     c.obs_waves = obs_waves
     c.obs_bins = obs_bins
     c.obs_cands = obs_cands
+    c.obs_road = obs_road
     return c
 
 

@@ -1,9 +1,9 @@
 """Autotuner for the launch shape of the fused step kernel.
 
-The kernel has four free parameters that do not change its results (the GPU tests check
+The kernel has five free parameters that do not change its results (the GPU tests check
 that every shape gives the same bits): waves per workgroup, number of distance bins of
-the top-K selection, candidate-list entries per wave, and the cell size of the per-world
-road grid.  Which shape is fastest depends on the batch (agents and road points per
+the top-K selection, candidate-list entries per wave, the cell size of the per-world road
+grid, and whether the road is staged in LDS or read through the caches.  Which shape is fastest depends on the batch (agents and road points per
 world, K) and on the device, so it is measured: every candidate shape steps the given
 scene a few times and the one with the lowest mean step time wins.
 
@@ -21,10 +21,11 @@ CACHE = os.environ.get("GD_TUNE_CACHE", os.path.join(os.path.dirname(os.path.abs
                                                      "tuned_shapes.json"))
 
 DEFAULT_SPACE = [
-    dict(obs_waves=w, obs_bins=b, obs_cands=c, cell_size=cs)
-    for (w, c) in ((16, 768), (16, 1024), (12, 768), (8, 768))
-    for b in (256, 512)
-    for cs in (10.0, 15.0, 20.0)
+    dict(obs_waves=w, obs_bins=b, obs_cands=c, cell_size=cs, obs_road=rd)
+    for rd in (1, 2)  # GD_ROAD_LDS, GD_ROAD_GLOBAL
+    for (w, c) in ((16, 512), (16, 768), (12, 768), (8, 768))
+    for b in (256, 512, 1024)
+    for cs in (10.0, 12.0, 15.0)
 ]
 
 

@@ -47,15 +47,22 @@ def test_cfg2_uneven_subset(gpu, oracle_mod):
     print("cfg2 subset:", st)
 
 
-@pytest.mark.parametrize("waves,bins,cands", [(1, 64, 256), (4, 128, 512), (16, 512, 1024), (2, 256, 128), (12, 256, 768)])
-def test_launch_shapes_bitwise_equal(gpu, waves, bins, cands):
+# (waves, bins, candidate entries, cell size, road mode 1 = staged in LDS / 2 = global);
+# every shape fits the LDS for 4000 road points per world
+SHAPES = [(1, 64, 256, 0.0, 2), (4, 128, 512, 0.0, 1), (8, 512, 1024, 0.0, 1), (2, 256, 128, 0.0, 2),
+          (12, 256, 768, 0.0, 1), (8, 1024, 512, 6.0, 1), (12, 512, 768, 25.0, 1), (16, 256, 512, 15.0, 1),
+          (16, 1024, 512, 12.0, 2), (16, 512, 128, 8.0, 2), (12, 1024, 1024, 0.0, 2)]
+
+
+@pytest.mark.parametrize("waves,bins,cands,cell,road", SHAPES)
+def test_launch_shapes_bitwise_equal(gpu, waves, bins, cands, cell, road):
     """Every launch shape of the observation kernel gives the same bits."""
     from paper_2408_01584_amd import scenes as S
     import torch
     sc = S.make_scene(1, worlds=3)
     acts = torch.as_tensor(S.make_actions(1, 3, sc.num_agents), device="cuda")
     ref = _sim(sc)
-    alt = _sim(sc, obs_waves=waves, obs_bins=bins, obs_cands=cands)
+    alt = _sim(sc, obs_waves=waves, obs_bins=bins, obs_cands=cands, cell_size=cell, obs_road=road)
     for k in range(3):
         ref.step(acts[k])
         alt.step(acts[k])
