@@ -43,6 +43,10 @@ def parse():
                     help="replay a HIP graph per step instead of launching the kernel directly")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
+    ap.add_argument("--config", type=int, default=1, choices=(0, 1, 2, 3, 4),
+                    help="1 (default): the headline workload; 0, 2, 3, 4: the secondary "
+                         "workloads (latency, uneven batch, differentiable rollout, LIDAR + "
+                         "rollout at 4096 worlds), one JSON line each")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc output folders (FETCH_SIZE, WRITE_SIZE) of a "
                          "--copy-calibration run into the HBM-traffic record, then exit")
@@ -110,6 +114,9 @@ def main():
               "no exchange between GPUs, and this build measures one GPU's share (--gpus 1).",
               file=sys.stderr)
         sys.exit(2)
+    if args.config != 1:
+        secondary(args)
+        return
     import numpy as np
     import torch
 
@@ -220,6 +227,97 @@ def main():
         out["copy_calibration_bytes"] = 2 * a.numel() * 4
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg_id, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+def _timed(fn, reps=5):
+    """Median over `reps` event-timed calls of fn() on the current stream (ms)."""
+    import torch
+    out = []
+    for _ in range(reps):
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0.record()
+        fn()
+        t1.record()
+        torch.cuda.synchronize()
+        out.append(t0.elapsed_time(t1))
+    return sorted(out)[len(out) // 2]
+
+
+def secondary(args):
+    """Secondary workloads: config 0 (one world, launch latency), 2 (1024 uneven worlds,
+    direct launches against a HIP graph per step), 3 (512 x 32, T = 20: step, and the
+    differentiable rollout forward against forward + backward) and 4 (4096 x 64 with
+    30-ray LIDAR, T = 91 rollout with checkpoints every 10 steps).  Median of 5 repeats."""
+    import torch
+
+    from paper_2408_01584_amd import scenes as S
+    from paper_2408_01584_amd.sim import Sim
+
+    c = args.config
+    torch.cuda.set_device(0)
+    print("[bench] generating workload %d" % c, file=sys.stderr, flush=True)
+    scene = S.make_scene(c)
+    print("[bench] workload %d ready: %d worlds, %d agents" % (c, scene.num_worlds, scene.num_agents),
+          file=sys.stderr, flush=True)
+    p = scene.params
+    A, W = scene.num_agents, scene.num_worlds
+    T = S.CONFIGS[c].steps
+    acts = torch.as_tensor(S.make_actions(c, T + 10, A), device="cuda")
+    out = {"metric": "agent-steps/sec (full step) on 1 MI355X", "config_id": c, "worlds": W,
+           "agents": A, "road_points": scene.num_road, "top_k": p.top_k, "partners": p.partners,
+           "lidar_rays": p.lidar_rays, "steps": T, "unit": "agent-steps/s"}
+
+    def run_steps(sim, n):
+        def f():
+            for k in range(n):
+                sim.step(acts[k])
+        return f
+
+    modes = (("direct", False), ("graph", True)) if c in (0, 2) else (("direct", False),)
+    for name, graph in modes:
+        sim = Sim(scene, graph=graph)
+        run_steps(sim, 10)()
+        ms = _timed(run_steps(sim, T))
+        out[name] = {"ms_per_step": round(ms / T, 5), "value": round(A * T / (ms / 1e3), 1)}
+        if name == "direct":
+            out["value"] = out[name]["value"]
+            out["ms_per_step"] = out[name]["ms_per_step"]
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+
+    if c in (3, 4):
+        C = 10
+        sim = Sim(scene)
+        ra = acts[:T].contiguous()
+        rewards, ckpt = sim.rollout_fwd(ra, C)
+        gr = torch.ones_like(rewards)
+        sim.rollout_bwd(ra, ckpt, gr, C)
+        fwd = _timed(lambda: sim.rollout_fwd(ra, C))
+        rewards, ckpt = sim.rollout_fwd(ra, C)
+
+        def fb():
+            r, ck = sim.rollout_fwd(ra, C)
+            sim.rollout_bwd(ra, ck, gr, C)
+        fwdbwd = _timed(fb)
+        torch.cuda.synchronize()
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        fb()
+        torch.cuda.synchronize()
+        peak_ck = torch.cuda.max_memory_allocated() - base
+        out["rollout"] = {
+            "T": T, "ckpt_every": C,
+            "fwd_agent_steps_per_s": round(A * T / (fwd / 1e3), 1),
+            "fwd_bwd_agent_steps_per_s": round(A * T / (fwdbwd / 1e3), 1),
+            "fwd_bwd_over_fwd_time": round(fwdbwd / fwd, 3),
+            "checkpoint_bytes": int(ckpt.numel() * 4),
+            "checkpoint_bytes_every_step": int(T * 4 * A * 4),
+            "peak_extra_bytes_fwd_bwd": int(peak_ck)}
+        sim.close()
     print(json.dumps(out), flush=True)
 
 

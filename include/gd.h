@@ -102,7 +102,7 @@ typedef struct {
     float v_max;               /* speed clip (m/s) > 0 */
     float lidar_range;         /* LIDAR range (m) > 0 when lidar_rays > 0 */
     float collision_penalty;   /* reward -= penalty when the agent collided */
-    float cell_size;           /* road grid cell (m); 0 = library default (12 m) */
+    float cell_size;           /* road grid cell (m); 0 = library default (15 m) */
     int32_t obs_waves;         /* launch shape of the step kernel: waves per workgroup
                                   (1, 2, 4, 8, 12, 16; 0 = the shape with the most
                                   resident waves per compute unit that fits the LDS) */
@@ -112,9 +112,10 @@ typedef struct {
                                   (128, 256, 384, 512, 768, 1024; 0 = chosen with
                                   obs_waves; agents with more candidates rescan the grid) */
     int32_t obs_road;          /* where the step kernel reads a world's road points:
-                                  GD_ROAD_AUTO, GD_ROAD_LDS (staged in LDS for the whole
-                                  step; needs room for 16 B per point) or GD_ROAD_GLOBAL
-                                  (from the workspace through the caches) */
+                                  GD_ROAD_LDS (staged in LDS for the whole step; needs
+                                  16 B per point of the largest world), GD_ROAD_GLOBAL
+                                  (from the workspace through the caches) or GD_ROAD_AUTO
+                                  (staged when that keeps as many resident waves) */
     int32_t reserved;          /* must be zero */
 } gd_config;
 

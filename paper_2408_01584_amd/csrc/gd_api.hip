@@ -15,7 +15,7 @@
 #include "gd_internal.h"
 
 namespace gdk {
-hipError_t launch_lidar_impl(const SimArgs &a, int max_agents, hipStream_t s);
+hipError_t launch_lidar_impl(const SimArgs &a, const LidarCtl &lc, hipStream_t s);
 hipError_t launch_rollout_fwd_impl(const SimArgs &a, const float2 *actions, int T, int C,
                                    float *rewards, float *ckpt, hipStream_t s);
 hipError_t launch_rollout_bwd_impl(const SimArgs &a, const float2 *actions, const float *ckpt,
@@ -23,7 +23,7 @@ hipError_t launch_rollout_bwd_impl(const SimArgs &a, const float2 *actions, cons
                                    float *grad_state0, hipStream_t s);
 bool step_kernel_node(const SimArgs *a, const StepCtl *c, int waves, int bins,
                       hipKernelNodeParams &p, void **args);
-bool lidar_kernel_node(const SimArgs *a, int max_agents, hipKernelNodeParams &p, void **args);
+bool lidar_kernel_node(const SimArgs *a, const LidarCtl *lc, hipKernelNodeParams &p, void **args);
 
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
@@ -43,6 +43,7 @@ Layout make_layout(int W, long long A, long long R) {
     L.eseg = take(sizeof(float4) * (size_t)R);
     L.eseg_id = take(sizeof(int) * (size_t)R);
     L.snap = take(sizeof(float4) * (size_t)A);
+    L.kth = take(sizeof(float) * (size_t)A);
     L.pbase = take(sizeof(long long) * (size_t)W);
     L.err = take(256);
     L.order = take(sizeof(int) * (size_t)W);
@@ -66,6 +67,7 @@ struct gd_sim {
     std::vector<int32_t> h_agent_off, h_road_off;
     Layout lay;
     StepCtl ctl{};  // launch shape of the fused step (mode and pointers set per call)
+    LidarCtl lctl{};  // launch shape of the LIDAR kernel
     int waves = 16, bins = 256;
     int max_road = 0, max_agents = 0;
     long long slots = 0;
@@ -163,26 +165,26 @@ static long long partner_slots_of(const gd_config *c, const int32_t *h_agent_off
 // entries per wave, and whether the road is staged in LDS.  Fields the config fixes are
 // kept; the rest maximise resident waves per compute unit (counting only the workgroups
 // the batch can fill), then prefer 512 bins, a candidate list of at least 512 entries
-// (the smallest such), and staged edge segments.  GD_ROAD_AUTO reads the road through the
-// caches, which leaves the LDS to larger per-wave buffers; GD_ROAD_LDS stages it.
-static bool launch_shape(const gd_config *c, int max_road, int max_cells, int max_edges,
-                         int max_agents, int &waves, int &bins, int &road_cap, int &edge_cap,
-                         int &cand_cap, int &idx16) {
+// (the smallest such), and staged edge segments.  GD_ROAD_AUTO stages the road when that
+// keeps as many resident waves as reading it through the caches (the road then costs no
+// memory round trips in the observation phase), else reads it through the caches.
+struct Shape {
+    long score = -1;
+    int waves = 0, bins = 0, cand_cap = 0, edge_cap = 0, road_cap = 0, resident = 0;
+};
+
+static Shape best_shape(const gd_config *c, bool staged, int max_road, int cell_cap4,
+                        int max_edges, int agent_cap, bool idx16) {
     const int K = c->top_k;
-    idx16 = max_road < 65536 ? 1 : 0;
-    const int agent_cap = std::max(max_agents, 1);
-    const int cell_cap4 = (max_cells + 1 + 3) / 4 * 4;
     const int wgs_needed = std::max(1, (c->num_worlds + 255) / 256);
     const int wave_opts[] = {16, 12, 8, 4, 2, 1};
     const int cand_opts[] = {1024, 768, 512, 384, 256, 128};
     const int bin_opts[] = {512, 1024, 256, 128, 64};
     auto bin_pref = [](int b) { return b == 512 ? 5 : b == 1024 ? 4 : b == 256 ? 3 : b == 128 ? 2 : 1; };
     auto cand_pref = [](int cc) { return cc == 512 ? 3 : cc == 768 ? 2 : cc == 1024 ? 1 : 0; };
-    const bool staged = c->obs_road == GD_ROAD_LDS && K > 0;
-    if (staged && (max_road > 60000 || !idx16)) return false;
+    Shape best;
     // a multiple of 4 points keeps the LDS regions after the road 16-byte aligned
     const int rc = staged ? (std::max(max_road, 1) + 3) / 4 * 4 : 0;
-    long best = -1;
     for (int ec : {max_edges, 0}) {
         for (int wv : wave_opts) {
             if (c->obs_waves && wv != c->obs_waves) continue;
@@ -191,23 +193,45 @@ static bool launch_shape(const gd_config *c, int max_road, int max_cells, int ma
                 for (int cc : cand_opts) {
                     if (c->obs_cands && cc != c->obs_cands) continue;
                     const size_t lds = step_lds_bytes(wv, nb, K, K ? cc : 0, rc, cell_cap4, ec,
-                                                      agent_cap, idx16 != 0);
+                                                      agent_cap, idx16);
                     if (lds > (size_t)kLdsBytes) continue;
                     const int wgs = std::min({(int)((size_t)kLdsBytes / lds), 32 / wv, wgs_needed});
                     const long score = (long)wgs * wv * 1000 + bin_pref(nb) * 20 + cand_pref(cc) * 4 + (ec ? 1 : 0);
-                    if (score > best) {
-                        best = score;
-                        waves = wv;
-                        bins = nb;
-                        cand_cap = K ? cc : 0;
-                        edge_cap = ec;
+                    if (score > best.score) {
+                        best.score = score;
+                        best.waves = wv;
+                        best.bins = nb;
+                        best.cand_cap = K ? cc : 0;
+                        best.edge_cap = ec;
+                        best.road_cap = rc;
+                        best.resident = wgs * wv;
                     }
                 }
             }
         }
     }
-    road_cap = rc;
-    return best >= 0;
+    return best;
+}
+
+static bool launch_shape(const gd_config *c, int max_road, int max_cells, int max_edges,
+                         int max_agents, int &waves, int &bins, int &road_cap, int &edge_cap,
+                         int &cand_cap, int &idx16) {
+    idx16 = max_road < 65536 ? 1 : 0;
+    const int agent_cap = std::max(max_agents, 1);
+    const int cell_cap4 = (max_cells + 1 + 3) / 4 * 4;
+    const bool can_stage = c->top_k > 0 && idx16 && max_road <= 60000;
+    Shape glob, lds;
+    if (c->obs_road != GD_ROAD_LDS) glob = best_shape(c, false, max_road, cell_cap4, max_edges, agent_cap, idx16);
+    if (c->obs_road != GD_ROAD_GLOBAL && can_stage)
+        lds = best_shape(c, true, max_road, cell_cap4, max_edges, agent_cap, idx16);
+    const Shape &pick = (lds.score >= 0 && lds.resident >= glob.resident) ? lds : glob;
+    if (pick.score < 0) return false;
+    waves = pick.waves;
+    bins = pick.bins;
+    cand_cap = pick.cand_cap;
+    edge_cap = pick.edge_cap;
+    road_cap = pick.road_cap;
+    return true;
 }
 
 // workgroup order: costliest worlds first, so that the in-order dispatch of workgroups
@@ -263,7 +287,7 @@ static gd_status enqueue_step(gd_sim *sim, int mode, const float *actions, const
     c.mask = mask;
     TIMED(sim, s, GD_PHASE_STEP, launch_step(sim->args, c, sim->waves, sim->bins, s), "step launch");
     if (sim->args.N > 0 && sim->args.A > 0)
-        TIMED(sim, s, GD_PHASE_LIDAR, launch_lidar_impl(sim->args, sim->max_agents, s), "lidar launch");
+        TIMED(sim, s, GD_PHASE_LIDAR, launch_lidar_impl(sim->args, sim->lctl, s), "lidar launch");
     return GD_OK;
 }
 
@@ -279,7 +303,7 @@ static gd_status graph_step(gd_sim *sim, const float *actions, hipStream_t s) {
     if (!step_kernel_node(&sim->graph_args, &sim->graph_ctl, sim->waves, sim->bins, sp, sargs))
         return fail(GD_E_STATE, "no step kernel for this launch shape");
     const bool lidar = sim->args.N > 0 && sim->args.A > 0;
-    if (lidar && !lidar_kernel_node(&sim->graph_args, sim->max_agents, lp, largs))
+    if (lidar && !lidar_kernel_node(&sim->graph_args, &sim->lctl, lp, largs))
         return fail(GD_E_STATE, "no lidar kernel");
     if (!sim->graph_exec) {
         HIP_TRY(hipGraphCreate(&sim->graph, 0), "graph create");
@@ -432,6 +456,7 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
     a.eseg = (float4 *)(ws + L.eseg);
     a.eseg_id = (int *)(ws + L.eseg_id);
     a.snap = (float4 *)(ws + L.snap);
+    a.kth = (float *)(ws + L.kth);
     a.pbase = (long long *)(ws + L.pbase);
     a.err = (unsigned *)(ws + L.err);
     sim->ctl.order = (const int *)(ws + L.order);
@@ -494,10 +519,23 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
         sim->ctl.cell_cap4 = (max_cells + 1 + 3) / 4 * 4;
         sim->ctl.edge_cap = edge_cap;
         sim->ctl.cand_cap = cand_cap;
+        // LIDAR: the world's agents, and its edge segments when they fit, staged in LDS
+        sim->lctl.agent_cap = std::max(max_agents, 1);
+        sim->lctl.cell_cap4 = sim->ctl.cell_cap4;
+        sim->lctl.waves = kLidarMaxWaves;
+        sim->lctl.edge_cap = max_edges;
+        if (cfg->lidar_rays > 0 && lidar_lds_bytes(cfg->lidar_rays, sim->lctl) > (size_t)kLdsBytes)
+            sim->lctl.edge_cap = 0;
+        if (cfg->lidar_rays > 0 && lidar_lds_bytes(cfg->lidar_rays, sim->lctl) > (size_t)kLdsBytes) {
+            delete sim;
+            return fail(GD_E_SIZE, "LIDAR: %d rays and %d agents per world do not fit the LDS",
+                        cfg->lidar_rays, max_agents);
+        }
         // an identity order needs no indirection
         bool identity = true;
         for (int w = 0; w < W; w++) identity = identity && order[w] == w;
         if (identity) sim->ctl.order = nullptr;
+        sim->lctl.order = sim->ctl.order;
     }
     st = enqueue_step(sim, kModeReset, nullptr, nullptr, s);
     if (st != GD_OK) {

@@ -13,7 +13,7 @@ constexpr int kWave = 64;
 constexpr int kGridAxis = GD_GRID_MAX_CELLS_PER_AXIS;        // cells per axis, at most
 constexpr int kGridCells = kGridAxis * kGridAxis;            // cells per world, at most
 constexpr int kCellStride = kGridCells + 1;                  // CSR row length per world
-constexpr float kDefaultCell = 12.0f;
+constexpr float kDefaultCell = 15.0f;
 
 // Per-world uniform grid over the road points (and, separately, over the road-edge
 // segments keyed by their first endpoint).  Built once by gd_create.
@@ -58,6 +58,8 @@ struct SimArgs {
     float4 *eseg;      // [R] edge segments (x0, y0, x1, y1), cell-sorted
     int *eseg_id;      // [R] world-local index k of the segment (k, k+1)
     float4 *snap;      // [A] initial (x, y, yaw, speed)
+    float *kth;        // [A] key (binary32 d^2) of each agent's K-th road point at its last
+                       // observation, R^2 when it had fewer than K in the radius
     long long *pbase;  // [W] first partner slot of each world
     unsigned *err;     // device error word
 };
@@ -82,9 +84,20 @@ struct StepCtl {
     int cand_cap;              // candidate list entries per wave
 };
 
+// Launch control of the LIDAR kernel (one workgroup per world).
+constexpr int kLidarMaxWaves = 8;
+struct LidarCtl {
+    const int *order;  // [W] world of each workgroup, NULL = identity
+    int agent_cap;     // agents per world staged in LDS
+    int edge_cap;      // edge segments per world staged in LDS (0 = read from global)
+    int cell_cap4;     // LDS slots for a world's edge-grid cell starts
+    int waves;         // waves per workgroup (1..kLidarMaxWaves)
+};
+size_t lidar_lds_bytes(int N, const LidarCtl &lc);
+
 // Workspace layout (byte offsets, each 256-aligned).
 struct Layout {
-    size_t grid, cell_start, pt_xy, pt_aux, ecell_start, eseg, eseg_id, snap, pbase, err, order,
+    size_t grid, cell_start, pt_xy, pt_aux, ecell_start, eseg, eseg_id, snap, kth, pbase, err, order,
         total;
 };
 Layout make_layout(int W, long long A, long long R);

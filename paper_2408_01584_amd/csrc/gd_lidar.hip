@@ -5,17 +5,18 @@
 // the nearest hit in (0, range] on a road-edge segment (type 1) or on a side of another
 // visible agent's box (type 2), else (range, 0).
 //
-// One wave per agent, lanes over the candidate segments: road-edge segments keyed in the
-// grid rows that meet the disc of radius range + longest segment, then the four sides of
-// every other visible agent within range.  Each candidate is moved into the ego frame,
-// the arc it subtends gives the (few) rays it can meet, and each of those rays is
-// intersected exactly; a per-ray 64-bit LDS minimum over (distance bits, type) keeps the
-// nearest hit (ties: road edge first).
+// One workgroup per world.  The world's agents (position, heading, half extents, flags)
+// and, when they fit, its edge segments with their grid rows are staged in LDS first, so
+// the per-agent loop reads nothing from global memory.  Then one wave per agent, lanes
+// over the candidate segments: edge segments keyed in the grid rows that meet the disc of
+// radius range + longest segment, then the four sides of every other visible agent within
+// range.  Each candidate is moved into the ego frame, the arc it subtends gives the (few)
+// rays it can meet, widened by one ray on each side, and each of those rays is intersected
+// exactly; a per-ray 64-bit LDS minimum over (distance bits, type) keeps the nearest hit
+// (ties: road edge first).
 #include "gd_internal.h"
 
 namespace gdk {
-
-constexpr int kLidarWaves = 4;
 
 __device__ __forceinline__ void lidar_candidate(float ax, float ay, float bx, float by,
                                                 unsigned type, int N, float inv_step,
@@ -55,46 +56,103 @@ __device__ __forceinline__ void lidar_candidate(float ax, float ay, float bx, fl
     }
 }
 
-__global__ __launch_bounds__(kLidarWaves * kWave) void k_lidar(SimArgs a, const int *__restrict__ order) {
+__device__ __forceinline__ float lidar_uniform(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// LDS layout of one workgroup (byte offsets, 16-aligned regions)
+struct LidarLds {
+    size_t dirs, best, agents, edges, ecells, total;
+};
+
+__host__ __device__ inline LidarLds lidar_layout(int N, int waves, int agent_cap, int edge_cap,
+                                                 int cell_cap4) {
+    auto up = [](size_t b) { return (b + 15) / 16 * 16; };
+    LidarLds L;
+    L.dirs = 0;
+    L.best = up((size_t)N * 8);
+    L.agents = L.best + up((size_t)waves * N * 8);
+    // x, y, cos, sin, half length, half width, half diagonal, flags
+    L.edges = L.agents + up((size_t)agent_cap * 4 * 8);
+    L.ecells = L.edges + (size_t)edge_cap * 16;
+    L.total = L.ecells + (edge_cap ? up((size_t)cell_cap4 * 4) : 0);
+    return L;
+}
+
+__global__ __launch_bounds__(kLidarMaxWaves * kWave) void k_lidar(SimArgs a, LidarCtl lc) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = a.N;
-    float2 *dirs = reinterpret_cast<float2 *>(smem);
-    const int wid = threadIdx.x / kWave;
+    const int nwaves = blockDim.x / kWave;
+    const LidarLds L = lidar_layout(N, nwaves, lc.agent_cap, lc.edge_cap, lc.cell_cap4);
+    float2 *dirs = reinterpret_cast<float2 *>(smem + L.dirs);
+    const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     const int lane = threadIdx.x & (kWave - 1);
-    unsigned long long *best = reinterpret_cast<unsigned long long *>(dirs + N) + (size_t)wid * N;
-    const int w = order ? order[blockIdx.x] : (int)blockIdx.x;
+    unsigned long long *best = reinterpret_cast<unsigned long long *>(smem + L.best) + (size_t)wid * N;
+    const int ac = lc.agent_cap;
+    float *sx = reinterpret_cast<float *>(smem + L.agents);
+    float *sy = sx + ac, *sc = sx + 2 * ac, *ss = sx + 3 * ac, *shl = sx + 4 * ac,
+          *shw = sx + 5 * ac, *sdg = sx + 6 * ac;
+    int *sf = reinterpret_cast<int *>(sx + 7 * ac);
+    float4 *sedge = reinterpret_cast<float4 *>(smem + L.edges);
+    int *secells = reinterpret_cast<int *>(smem + L.ecells);
+
+    const int w = lc.order ? lc.order[blockIdx.x] : (int)blockIdx.x;
     const int a0 = a.agent_off[w];
     const int n = a.agent_off[w + 1] - a0;
     const int r0 = a.road_off[w];
     const WorldGrid g = a.grid[w];
-    const int *ecs = a.ecell_start + (size_t)w * kCellStride;
-    const float4 *es = a.eseg + r0;
+    const int ncell = g.nx * g.ny;
+    const bool staged = lc.edge_cap > 0;
     const float range = a.lidar_range;
     const float inv_step = (float)N / 6.283185307179586f;
+
+    // staging: ray directions, the world's agents, its edge segments and their grid rows
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
         float s, c;
         sincosf(6.283185307179586f * (float)k / (float)N, &s, &c);
         dirs[k] = make_float2(c, s);
     }
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const int gi = a0 + i;
+        const float yaw = a.yaw[gi];
+        const float hl = 0.5f * a.len[gi], hw = 0.5f * a.wid[gi];
+        float s, c;
+        sincosf(yaw, &s, &c);
+        sx[i] = a.x[gi];
+        sy[i] = a.y[gi];
+        sc[i] = c;
+        ss[i] = s;
+        shl[i] = hl;
+        shw[i] = hw;
+        sdg[i] = sqrtf(hl * hl + hw * hw);
+        sf[i] = a.fl[gi];
+    }
+    if (staged) {
+        for (int k = threadIdx.x; k < g.n_edge; k += blockDim.x) sedge[k] = a.eseg[r0 + k];
+        const int *ec0 = a.ecell_start + (size_t)w * kCellStride;
+        for (int k = threadIdx.x; k <= ncell; k += blockDim.x) secells[k] = ec0[k];
+    }
     __syncthreads();
+
+    const int *ecs = staged ? secells : a.ecell_start + (size_t)w * kCellStride;
+    const float4 *es = staged ? sedge : a.eseg + r0;
     const float reach = range + g.max_seg + 1e-3f * g.cs + 1e-3f;
-    for (int l = wid; l < n; l += kLidarWaves) {
+    for (int l = wid; l < n; l += nwaves) {
         const int ai = a0 + l;
         float *out = a.lidar + (size_t)ai * N;
         int *hit = a.lidar_hit + (size_t)ai * N;
-        if (!(a.fl[ai] & GD_FLAG_VISIBLE)) {
+        if (!(__builtin_amdgcn_readfirstlane(sf[l]) & GD_FLAG_VISIBLE)) {
             for (int k = lane; k < N; k += kWave) {
                 out[k] = 0.0f;
                 hit[k] = 0;
             }
             continue;
         }
-        const float px = a.x[ai], py = a.y[ai];
-        float sn, cs;
-        sincosf(a.yaw[ai], &sn, &cs);
+        const float px = lidar_uniform(sx[l]), py = lidar_uniform(sy[l]);
+        const float cs = lidar_uniform(sc[l]), sn = lidar_uniform(ss[l]);
         const unsigned long long none = ((unsigned long long)__float_as_uint(range) << 32) | 0u;
         for (int k = lane; k < N; k += kWave) best[k] = ~0ull;
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
         // road-edge segments keyed in the rows that meet the disc of radius `reach`
         if (g.n_edge > 0) {
@@ -119,25 +177,23 @@ __global__ __launch_bounds__(kLidarWaves * kWave) void k_lidar(SimArgs a, const 
         // sides of the other visible agents' boxes
         for (int e = lane; e < 4 * n; e += kWave) {
             const int j = e >> 2, side = e & 3;
-            if (j == l) continue;
-            const int gj = a0 + j;
-            if (!(a.fl[gj] & GD_FLAG_VISIBLE)) continue;
-            const float xj = a.x[gj], yj = a.y[gj];
-            const float hl = 0.5f * a.len[gj], hw = 0.5f * a.wid[gj];
-            const float rr = range + sqrtf(hl * hl + hw * hw) + 1e-3f;
-            const float dxj = xj - px, dyj = yj - py;
+            if (j == l || !(sf[j] & GD_FLAG_VISIBLE)) continue;
+            const float dxj = sx[j] - px, dyj = sy[j] - py;
+            const float rr = range + sdg[j] + 1e-3f;
             if (dxj * dxj + dyj * dyj > rr * rr) continue;
-            float sj, cj;
-            sincosf(a.yaw[gj], &sj, &cj);
+            const float cj = sc[j], sj = ss[j], hl = shl[j], hw = shw[j];
             // corners (+hl,+hw) (+hl,-hw) (-hl,-hw) (-hl,+hw); side k joins corner k and k+1
-            const float cxs[4] = {hl, hl, -hl, -hl}, cys[4] = {hw, -hw, -hw, hw};
-            const int c0i = side, c1i = (side + 1) & 3;
-            const float ux0 = dxj + cj * cxs[c0i] - sj * cys[c0i], uy0 = dyj + sj * cxs[c0i] + cj * cys[c0i];
-            const float ux1 = dxj + cj * cxs[c1i] - sj * cys[c1i], uy1 = dyj + sj * cxs[c1i] + cj * cys[c1i];
+            const float ax0 = (side == 0 || side == 1) ? hl : -hl;
+            const float ay0 = (side == 0 || side == 3) ? hw : -hw;
+            const int side1 = (side + 1) & 3;
+            const float ax1 = (side1 == 0 || side1 == 1) ? hl : -hl;
+            const float ay1 = (side1 == 0 || side1 == 3) ? hw : -hw;
+            const float ux0 = dxj + cj * ax0 - sj * ay0, uy0 = dyj + sj * ax0 + cj * ay0;
+            const float ux1 = dxj + cj * ax1 - sj * ay1, uy1 = dyj + sj * ax1 + cj * ay1;
             lidar_candidate(cs * ux0 + sn * uy0, -sn * ux0 + cs * uy0, cs * ux1 + sn * uy1,
                             -sn * ux1 + cs * uy1, 2u, N, inv_step, range, dirs, best);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
         for (int k = lane; k < N; k += kWave) {
             unsigned long long b = best[k];
@@ -145,37 +201,43 @@ __global__ __launch_bounds__(kLidarWaves * kWave) void k_lidar(SimArgs a, const 
             out[k] = __uint_as_float((unsigned)(b >> 32));
             hit[k] = (int)(b & 0xffffffffu);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }
 }
 
-static size_t lidar_lds(int N) { return (size_t)N * 8 + (size_t)kLidarWaves * N * 8; }
+size_t lidar_lds_bytes(int N, const LidarCtl &lc) {
+    return lidar_layout(N, lc.waves, lc.agent_cap, lc.edge_cap, lc.cell_cap4).total;
+}
 
-hipError_t launch_lidar_impl(const SimArgs &a, int, hipStream_t s) {
-    if (a.N <= 0 || a.W <= 0) return hipSuccess;
-    const size_t lds = lidar_lds(a.N);
+static hipError_t lidar_prepare(size_t lds) {
     static size_t allowed = 0;
     if (lds > allowed) {
         hipError_t e = hipFuncSetAttribute((const void *)k_lidar, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         allowed = lds;
     }
-    hipLaunchKernelGGL(k_lidar, dim3(a.W), dim3(kLidarWaves * kWave), lds, s, a, (const int *)nullptr);
+    return hipSuccess;
+}
+
+hipError_t launch_lidar_impl(const SimArgs &a, const LidarCtl &lc, hipStream_t s) {
+    if (a.N <= 0 || a.W <= 0) return hipSuccess;
+    const size_t lds = lidar_lds_bytes(a.N, lc);
+    hipError_t e = lidar_prepare(lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_lidar, dim3(a.W), dim3(lc.waves * kWave), lds, s, a, lc);
     return hipGetLastError();
 }
 
-bool lidar_kernel_node(const SimArgs *a, int, hipKernelNodeParams &p, void **args) {
-    static const int *no_order = nullptr;
-    const size_t lds = lidar_lds(a->N);
-    if (hipFuncSetAttribute((const void *)k_lidar, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return false;
+bool lidar_kernel_node(const SimArgs *a, const LidarCtl *lc, hipKernelNodeParams &p, void **args) {
+    const size_t lds = lidar_lds_bytes(a->N, *lc);
+    if (lidar_prepare(lds) != hipSuccess) return false;
     p.func = (void *)k_lidar;
     p.gridDim = dim3(a->W);
-    p.blockDim = dim3(kLidarWaves * kWave);
+    p.blockDim = dim3(lc->waves * kWave);
     p.sharedMemBytes = (unsigned)lds;
     args[0] = (void *)a;
-    args[1] = (void *)&no_order;
+    args[1] = (void *)lc;
     p.kernelParams = args;
     p.extra = nullptr;
     return true;

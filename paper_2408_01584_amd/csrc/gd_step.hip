@@ -180,7 +180,7 @@ __host__ __device__ inline size_t wave_lds_bytes(int NB, int K, int ccap, bool i
     return (b + 15) / 16 * 16;
 }
 
-constexpr int kAgentArrays = 12;  // x y yaw v L W cos sin goal_x goal_y flags coll
+constexpr int kAgentArrays = 13;  // x y yaw v L W cos sin goal_x goal_y flags coll bound
 
 // Road modes of the step kernel: where phase 5 reads the road, and the index width.
 enum RoadMode { kRoadGlobal32 = 0, kRoadGlobal16 = 1, kRoadLds = 2 };
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     const int tid = threadIdx.x;
     const int bs = blockDim.x;
     const int nwaves = bs / kWave;
-    const int wid = tid / kWave;
+    const int wid = __builtin_amdgcn_readfirstlane(tid / kWave);  // wave-uniform for the compiler
     const int lane = tid & (kWave - 1);
     const int a0 = a.agent_off[w];
     const int n = a.agent_off[w + 1] - a0;
@@ -224,6 +224,7 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     float *sgx = sag + 8 * ac, *sgy = sag + 9 * ac;
     int *sf = reinterpret_cast<int *>(sag + 10 * ac);
     int *scoll = reinterpret_cast<int *>(sag + 11 * ac);
+    float *sbound = sag + 12 * ac;  // bound on the distance of the agent's K-th road point
     unsigned char *uni = reinterpret_cast<unsigned char *>(sag + kAgentArrays * ac);
     float4 *sedge = reinterpret_cast<float4 *>(uni);
     int *secells = reinterpret_cast<int *>(sedge + c.edge_cap);
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     int t = a.t[w];
     struct AgentIn {
         uint8_t f;
-        float x, y, yaw, v, L, W, gx, gy;
+        float x, y, yaw, v, L, W, gx, gy, kth;
         float2 act;
     };
     auto load_agent = [&](int i) {
@@ -256,6 +257,7 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
         in.W = a.wid[gi];
         in.gx = a.gx[gi];
         in.gy = a.gy[gi];
+        in.kth = a.kth[gi];
         // the action is read for every agent (no dependence on the flags load)
         in.act = mode == kModeStep ? c.actions[gi] : make_float2(0.f, 0.f);
         return in;
@@ -339,6 +341,10 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             ss[i] = sn;
             sf[i] = f;
             scoll[i] = 0;
+            // the K-th road point of the last observation lies within sqrt(kth) + |moved|
+            // of the new position (road points do not move); a reset invalidates it
+            const float mx = x - in.x, my = y - in.y;
+            sbound[i] = mode == kModeReset ? INFINITY : sqrtf(in.kth) + sqrtf(mx * mx + my * my);
         }
         if (nonfinite && (a.flags & GD_CHECK_FINITE)) atomicOr(a.err, 1u);
     }
@@ -456,6 +462,7 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             sincosf(s0.z, &sn, &cs);
             sc[i] = cs;
             ss[i] = sn;
+            sbound[i] = INFINITY;
             const int keep = keep_outcome ? (scoll[i] & (GD_FLAG_COLL_AGENT | GD_FLAG_COLL_EDGE |
                                                          GD_FLAG_GOAL | GD_FLAG_DONE))
                                           : 0;
@@ -492,10 +499,10 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     const float2 *rxy = STAGED ? sroad : (a.pt_xy + r0);
     const float2 *aux = STAGED ? saux : (a.pt_aux + r0);  // (direction, local index | type << 24)
     const int *cst = STAGED ? scells : (a.cell_start + (size_t)w * kCellStride);
-    const float R = a.R_obs, R2 = a.R2_obs;
-    const float bscale = (float)NB / R2;
+    const float R2 = a.R2_obs;
     const float marg = 1e-3f * g.cs + 1e-3f;
     constexpr int SH = PointIndex<IDX16>::kShift;
+    constexpr int SU = 4;  // chunks (scan) and entries (scatter) per lane in flight together
     const cand_t qmask = (cand_t)((1ull << SH) - 1);
 
     const long long pbase_w = a.P >= 0 ? 0 : a.pbase[w];
@@ -538,61 +545,78 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
                 out[s] = make_float4(0.f, 0.f, 0.f, 0.f);
                 oidx[s] = -1;
             }
+            if (lane == 0) a.kth[ai] = R2;
             continue;
         }
-        for (int b = lane; b < NB; b += kWave) hist[b] = 0;
-        // a. candidate rows: lane r holds the span [q0, q1) of grid row rlo + r and its
-        //    place [end - len, end) in the concatenation of all the spans
-        const int rlo = cell_coord(py - R, g.oy, g.inv_cs, g.ny);
-        const int rhi = cell_coord(py + R, g.oy, g.inv_cs, g.ny);
-        const int nrows = rhi - rlo + 1;  // at most kGridAxis
-        int q0 = 0, q1 = 0;
-        if (lane < nrows) row_span(g, cst, rlo + lane, px, py, R, marg, q0, q1);
-        const int len = q1 - q0;
-        const int end = wave_incl_scan(len);
-        const int M = __builtin_amdgcn_readlane(end, kWave - 1);
-        const int off = end - len;
-        const int delta = q0 - off;  // point = position + delta inside the row
+        // Pruned radius: when at least K points lie within Re <= R, the top K within R are
+        // exactly the top K within Re (every point beyond Re ranks after those K).  Re comes
+        // from the K-th key of the agent's last observation and how far it moved since
+        // (1 cm of slack); when fewer than K points fall within Re the selection is redone
+        // with the full radius, so the result never depends on the bound.
+        const float rb = wave_uniform(sbound[l]) + 0.01f;
+        float R2e = fminf(R2, rb * rb * 1.00002f);  // an infinite or NaN bound gives R2
+        float Re = 0.0f, bscale = 0.0f;
+        int nrows = 0, q0 = 0, q1 = 0, ncand = 0;
+        for (;;) {
+            Re = sqrtf(R2e);
+            bscale = (float)NB / R2e;
+            for (int b = lane; b < NB; b += kWave) hist[b] = 0;
+            // a. candidate rows: lane r holds the span [q0, q1) of grid row rlo + r and
+            //    its place [end - len, end) in the concatenation of all the spans
+            const int rlo = cell_coord(py - Re, g.oy, g.inv_cs, g.ny);
+            const int rhi = cell_coord(py + Re, g.oy, g.inv_cs, g.ny);
+            nrows = rhi - rlo + 1;  // at most kGridAxis
+            q0 = q1 = 0;
+            if (lane < nrows) row_span(g, cst, rlo + lane, px, py, Re, marg, q0, q1);
+            const int len = q1 - q0;
+            const int end = wave_incl_scan(len);
+            const int M = __builtin_amdgcn_readlane(end, kWave - 1);
+            const int off = end - len;
+            const int delta = q0 - off;  // point = position + delta inside the row
+            wave_sync();
 
-        // b. one pass over the concatenated spans, four chunks of 64 positions at a time
-        //    (their LDS loads in flight together): the key of each point; points within
-        //    the radius count in the histogram of bins (LDS atomics, nothing waits on
-        //    them) and go to the candidate list with their bin
-        int ncand = 0;
-        int r = 0;  // the first row that ends after the current chunk's start
-        // point of this lane's position in the chunk starting at b (< M): the row that
-        // holds position b, then the later rows that start inside the chunk
-        auto chunk_point = [&](int b) {
-            while (__builtin_amdgcn_readlane(end, r) <= b) r++;
-            const int p = b + lane;
-            int q = p + __builtin_amdgcn_readlane(delta, r);
-            for (int rr = r + 1; rr < nrows; rr++) {
-                const int o = __builtin_amdgcn_readlane(off, rr);
-                if (o >= b + kWave) break;
-                const int d = __builtin_amdgcn_readlane(delta, rr);
-                q = p >= o ? p + d : q;
+            // b. one pass over the concatenated spans, four chunks of 64 positions at a
+            //    time (their loads in flight together): the key of each point; points
+            //    within the radius count in the histogram of bins (LDS atomics, nothing
+            //    waits on them) and go to the candidate list with their bin
+            ncand = 0;
+            int r = 0;  // the first row that ends after the current chunk's start
+            // point of this lane's position in the chunk starting at b (< M): the row
+            // that holds position b, then the later rows that start inside the chunk
+            auto chunk_point = [&](int b) {
+                while (__builtin_amdgcn_readlane(end, r) <= b) r++;
+                const int p = b + lane;
+                int q = p + __builtin_amdgcn_readlane(delta, r);
+                for (int rr = r + 1; rr < nrows; rr++) {
+                    const int o = __builtin_amdgcn_readlane(off, rr);
+                    if (o >= b + kWave) break;
+                    const int d = __builtin_amdgcn_readlane(delta, rr);
+                    q = p >= o ? p + d : q;
+                }
+                return q;
+            };
+            for (int base = 0; base < M; base += SU * kWave) {
+                int qv[SU];
+                float2 pt[SU];
+#pragma unroll
+                for (int u = 0; u < SU; u++) qv[u] = base + u * kWave < M ? chunk_point(base + u * kWave) : 0;
+#pragma unroll
+                for (int u = 0; u < SU; u++) pt[u] = rxy[base + u * kWave + lane < M ? qv[u] : 0];
+#pragma unroll
+                for (int u = 0; u < SU; u++) {
+                    const float k = key32(px, py, pt[u].x, pt[u].y);
+                    const bool in = base + u * kWave + lane < M && k <= R2e;
+                    const int bn = bin_of(k, bscale, NB);
+                    if (in) atomicAdd(&hist[bn], 1);
+                    const unsigned long long bal = __ballot(in);
+                    const int pos = ncand + lane_prefix(bal);
+                    if (in && pos < ccap) cand[pos] = ((cand_t)bn << SH) | (cand_t)qv[u];
+                    ncand += __popcll(bal);
+                }
             }
-            return q;
-        };
-        constexpr int SU = 4;
-        for (int base = 0; base < M; base += SU * kWave) {
-            int qv[SU];
-            float2 pt[SU];
-#pragma unroll
-            for (int u = 0; u < SU; u++) qv[u] = base + u * kWave < M ? chunk_point(base + u * kWave) : 0;
-#pragma unroll
-            for (int u = 0; u < SU; u++) pt[u] = rxy[base + u * kWave + lane < M ? qv[u] : 0];
-#pragma unroll
-            for (int u = 0; u < SU; u++) {
-                const float k = key32(px, py, pt[u].x, pt[u].y);
-                const bool in = base + u * kWave + lane < M && k <= R2;
-                const int bn = bin_of(k, bscale, NB);
-                if (in) atomicAdd(&hist[bn], 1);
-                const unsigned long long bal = __ballot(in);
-                const int pos = ncand + lane_prefix(bal);
-                if (in && pos < ccap) cand[pos] = ((cand_t)bn << SH) | (cand_t)qv[u];
-                ncand += __popcll(bal);
-            }
+            if (ncand >= K || !(R2e < R2)) break;
+            R2e = R2;  // fewer than K within the pruned radius: the full radius
+            wave_sync();
         }
         const bool listed = ncand <= ccap;
         // points within the radius row by row (when the list overflowed)
@@ -603,7 +627,7 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
                 for (int qq = b0 + lane; qq < b1; qq += kWave) {
                     const float2 pt = rxy[qq];
                     const float k = key32(px, py, pt.x, pt.y);
-                    if (k <= R2) f(qq, k);
+                    if (k <= R2e) f(qq, k);
                 }
             }
         };
@@ -699,6 +723,7 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
         //    smaller key (branch-free); exact key ties are ordered by index in a second
         //    pass that only lanes with a tie take
         const int nstaged = overflow ? cut_start : need;
+        float kk = -1.0f;  // key of slot K - 1, on the lane that ranks it
         for (int p = lane; p < nstaged; p += kWave) {
             const float k = skey[p];
             const int q = sq[p];
@@ -720,6 +745,14 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             }
             const int fin = lo + rank;
             if (fin < K) perm[fin] = (idx_t)q;
+            kk = fin == K - 1 ? k : kk;
+        }
+        // the K-th key (R^2 when fewer than K points are in the radius), kept for the next
+        // step's pruned radius
+        float kth_key = R2;
+        {
+            const unsigned long long kb = __ballot(kk >= 0.0f);
+            if (kb) kth_key = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(kk), __ffsll((long long)kb) - 1));
         }
 
         if (overflow) {
@@ -738,6 +771,7 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
                 best = wave_min_u64(best);
                 prev = best;
                 first = false;
+                if (s == K - 1) kth_key = __uint_as_float((unsigned)(best >> 32));
                 if (lane == 0) {
                     const int idx = (int)(best & 0xffffffu);
                     const float dx = a.rx[r0 + idx] - px, dy = a.ry[r0 + idx] - py;
@@ -779,6 +813,7 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
                 }
             }
         }
+        if (lane == 0) a.kth[ai] = kth_key;
         wave_sync();
     }
 }
