@@ -44,6 +44,30 @@ def test_masked_reset(gpu, oracle_mod):
     compare_obs(g, o, sc.params.top_k)
 
 
+def test_pruned_radius_redo_after_external_move(gpu, oracle_mod):
+    """The road top-K searches a radius derived from each agent's previous K-th key and how
+    far it moved in the step.  Agents moved outside the step (the caller writing the state
+    buffers) can have fewer than K points within that radius, which must send them back to
+    the full radius: gd_obs after such a move, and the steps after it, match the oracle."""
+    from paper_2408_01584_amd import scenes as S
+    sc = S.make_scene(1, worlds=2)
+    acts = S.make_actions(1, 6, sc.num_agents)
+    sim = _sim(sc)
+    for k in range(3):
+        sim.step(torch.as_tensor(acts[k], device="cuda"))
+    b = sim.buf
+    b["x"][0::3] += 30.0   # into other parts of the map
+    b["y"][1::3] -= 60.0
+    b["x"][2::7] += 1000.0  # far from every road point: fewer than K in the full radius
+    sim.obs()
+    g = sim.host_outputs()
+    orc = oracle_for(sc, g["state"], g["flags"], g["t"], oracle_mod)
+    compare_obs(g, orc.obs(), sc.params.top_k)
+    assert (g["road_idx"][2::7] == -1).all()
+    st = teacher_forced_run(sc, sim, oracle_mod, acts[3:], 3)
+    print("after external move:", st)
+
+
 def test_padding_and_max_k(gpu, oracle_mod):
     """K = 960 (the maximum): every agent of the 500-point scene has fewer candidates."""
     from paper_2408_01584_amd import scenes as S
