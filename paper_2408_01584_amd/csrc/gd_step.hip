@@ -15,13 +15,16 @@
 // same kernel in other modes.
 //
 // Top-K without a sort, per agent:
+//   0. the search radius: the K-th key of the agent's last observation, grown by how far
+//      the agent moved, bounds a radius Re <= R that holds at least K points (road points
+//      do not move); if it holds fewer, the full radius R is searched;
 //   a. the grid rows that meet the disc are contiguous ranges of cell-sorted points; one
-//      lane computes each row's range;
-//   b. one scan: binary32 key d2 of every point in those ranges; points within the radius
-//      go to a per-wave candidate list (ballot compaction) and into a histogram of
-//      bin(d2) = floor(d2 * NB / R^2), a monotone function of d2;
+//      lane computes each row's range and a prefix sum concatenates them;
+//   b. one scan of the concatenation: binary32 key d2 of every point; points within the
+//      radius go into a histogram of bin(d2) = floor(d2 * NB / Re^2) (a monotone function
+//      of d2) and to a per-wave candidate list (ballot compaction);
 //   c. wave prefix scan of the histogram; the bin holding the K-th smallest key;
-//   d. the candidates of the bins up to that one are scattered bin by bin;
+//   d. the candidates of the bins up to that one are scattered bin by bin with their keys;
 //   e. rank = first slot of the bin + bin mates with smaller (d2, index): an exact order
 //      by (d2, index);
 //   f. the K slots are written in order as float4 rows (x', y', dir', type) + index.
