@@ -111,10 +111,9 @@ __device__ __forceinline__ void row_span(const WorldGrid &g, const int *cst, int
     q1 = cst[r * g.nx + c1 + 1];
 }
 
-__device__ __forceinline__ int bin_of(float k, float bscale, int NB) {
-    int b = (int)(k * bscale);
-    return b < NB - 1 ? b : NB - 1;
-}
+// bin of a key 0 <= k <= Re^2 with bscale = (NB - 1/2) / Re^2: k * bscale < NB even after
+// rounding, so no clamp is needed; monotone non-decreasing in k
+__device__ __forceinline__ int bin_of(float k, float bscale, int) { return (int)(k * bscale); }
 
 __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
 #pragma unroll
@@ -191,6 +190,8 @@ enum RoadMode { kRoadGlobal32 = 0, kRoadGlobal16 = 1, kRoadLds = 2 };
 template <int NB, int RM>
 __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int s_next_agent;  // phase 5 work counter
+    int *s_next = &s_next_agent;
     constexpr bool STAGED = RM == kRoadLds;
     constexpr bool IDX16 = RM != kRoadGlobal32;
     using idx_t = typename PointIndex<IDX16>::idx_t;
@@ -269,29 +270,28 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     AgentIn first{};
     if (a.A > 0) first = load_agent(min(tid, n - 1) < 0 ? -a0 : min(tid, n - 1));
 
-    // phase 0: the world's cell-sorted road points and grid rows into LDS (phase 5), and
-    // its edge segments with their grid rows (phase 2b) when they fit
+    // phase 0: the world's grid rows of road points (phase 5), and its edge segments with
+    // their grid rows (phase 2) when they fit, into LDS; then the loads of the first batch
+    // of its cell-sorted road points (phase 5), which are written to LDS only after the
+    // world phases so that their memory latency overlaps them
+    constexpr int U = 4;
+    const int nrd = (STAGED && K > 0) ? nr : 0;
+    const float2 *rsrc = a.pt_xy + r0;
+    const float2 *asrc = a.pt_aux + r0;
     {
-        const int nrd = (STAGED && K > 0) ? nr : 0;
         const int nrc = (STAGED && K > 0) ? ncell + 1 : 0;
         const int ned = (c.edge_cap && mode == kModeStep) ? g.n_edge : 0;
         const int nec = (c.edge_cap && mode == kModeStep) ? ncell + 1 : 0;
-        const float2 *rsrc = a.pt_xy + r0;
-        const float2 *asrc = a.pt_aux + r0;
         const int *csrc = a.cell_start + (size_t)w * kCellStride;
         const float4 *esrc = a.eseg + r0;
         const int *ecsrc = a.ecell_start + (size_t)w * kCellStride;
-        const int most = max(max(nrd, nrc), max(ned, nec));
-        constexpr int U = 4;
+        const int most = max(nrc, max(ned, nec));
         auto stage = [&](int b0) {
-            float2 rv[U], av[U];
             int cv[U], ecv[U];
             float4 ev[U];
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const int k = b0 + u * bs + tid;
-                rv[u] = k < nrd ? rsrc[k] : make_float2(0.f, 0.f);
-                av[u] = k < nrd ? asrc[k] : make_float2(0.f, 0.f);
                 cv[u] = k < nrc ? csrc[k] : 0;
                 ev[u] = k < ned ? esrc[k] : make_float4(0.f, 0.f, 0.f, 0.f);
                 ecv[u] = k < nec ? ecsrc[k] : 0;
@@ -299,10 +299,6 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
 #pragma unroll
             for (int u = 0; u < U; u++) {
                 const int k = b0 + u * bs + tid;
-                if (k < nrd) {
-                    sroad[k] = rv[u];
-                    saux[k] = av[u];
-                }
                 if (k < nrc) scells[k] = cv[u];
                 if (k < ned) sedge[k] = ev[u];
                 if (k < nec) secells[k] = ecv[u];
@@ -312,13 +308,21 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
         stage(0);
         for (int b0 = U * bs; b0 < most; b0 += U * bs) stage(b0);
     }
+    float2 rv0[U], av0[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        const int k = u * bs + tid;
+        rv0[u] = k < nrd ? rsrc[k] : make_float2(0.f, 0.f);
+        av0[u] = k < nrd ? asrc[k] : make_float2(0.f, 0.f);
+    }
 
-    // phase 1: agents into LDS, dynamics of the alive ones
+    // phase 1: agents into LDS, dynamics of the alive ones (the first agent of each thread
+    // from the loads issued above, in code of its own so that no merged register makes it
+    // wait for the road loads)
     {
         bool nonfinite = false;
-        for (int i = tid; i < n; i += bs) {
+        auto agent_phase1 = [&](int i, const AgentIn &in) {
             const int gi = a0 + i;
-            const AgentIn in = i == tid ? first : load_agent(i);
             const int f = in.f;
             float x = in.x, y = in.y, yaw = in.yaw, v = in.v;
             const float L = in.L;
@@ -348,7 +352,9 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             // of the new position (road points do not move); a reset invalidates it
             const float mx = x - in.x, my = y - in.y;
             sbound[i] = mode == kModeReset ? INFINITY : sqrtf(in.kth) + sqrtf(mx * mx + my * my);
-        }
+        };
+        if (tid < n) agent_phase1(tid, first);
+        for (int i = tid + bs; i < n; i += bs) agent_phase1(i, load_agent(i));
         if (nonfinite && (a.flags & GD_CHECK_FINITE)) atomicOr(a.err, 1u);
     }
     __syncthreads();
@@ -477,7 +483,23 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
         t = 0;
         if (mode == kModeReset && tid == 0) a.world_done[w] = 0;
     }
-    if (tid == 0) a.t[w] = t;
+    if (tid == 0) {
+        a.t[w] = t;
+        *s_next = 0;
+    }
+    // the road points loaded in phase 0, then the rest of a large world's road
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+        const int k = u * bs + tid;
+        if (k < nrd) {
+            sroad[k] = rv0[u];
+            saux[k] = av0[u];
+        }
+    }
+    for (int k = U * bs + tid; k < nrd; k += bs) {
+        sroad[k] = rsrc[k];
+        saux[k] = asrc[k];
+    }
     __syncthreads();
 
     // phase 4: ego observation
@@ -509,7 +531,14 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     const cand_t qmask = (cand_t)((1ull << SH) - 1);
 
     const long long pbase_w = a.P >= 0 ? 0 : a.pbase[w];
-    for (int l = wid; l < n; l += nwaves) {
+    // each wave starts with agent `wid` and then takes the next unclaimed agent, so that
+    // waves with cheap agents do not idle while others finish
+    auto next_agent = [&]() {
+        int v = 0;
+        if (lane == 0) v = atomicAdd(s_next, 1);
+        return nwaves + __builtin_amdgcn_readfirstlane(v);
+    };
+    for (int l = wid; l < n; l = next_agent()) {
         const int ai = a0 + l;
         const bool vis = (wave_uniform(sf[l]) & GD_FLAG_VISIBLE) != 0;
         const float px = wave_uniform(sx[l]), py = wave_uniform(sy[l]), yaw = wave_uniform(syaw[l]);
@@ -562,7 +591,7 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
         int nrows = 0, q0 = 0, q1 = 0, ncand = 0;
         for (;;) {
             Re = sqrtf(R2e);
-            bscale = (float)NB / R2e;
+            bscale = ((float)NB - 0.5f) / R2e;
             for (int b = lane; b < NB; b += kWave) hist[b] = 0;
             // a. candidate rows: lane r holds the span [q0, q1) of grid row rlo + r and
             //    its place [end - len, end) in the concatenation of all the spans
@@ -790,6 +819,8 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
         // f. the K slots in order, four per lane at a time so that their point loads
         //    are in flight together
         const int direct_end = overflow ? cut_start : nsel;
+        // road directions lie in [-pi, pi]: against the wrapped heading, one correction
+        const float yaw_w = wrap_pi(yaw);
         for (int s0 = 0; s0 < K; s0 += 4 * kWave) {
             float2 pt[4], x2[4];
 #pragma unroll
@@ -807,8 +838,11 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
                 if (s < direct_end) {
                     const int bits = __float_as_int(x2[u].y);
                     const float dx = pt[u].x - px, dy = pt[u].y - py;
-                    out[s] = make_float4(csy * dx + sny * dy, -sny * dx + csy * dy,
-                                         wrap_pi(x2[u].x - yaw), (float)((unsigned)bits >> 24));
+                    float dd = x2[u].x - yaw_w;
+                    dd = dd >= 3.14159265358979323846f ? dd - 6.283185307179586f : dd;
+                    dd = dd < -3.14159265358979323846f ? dd + 6.283185307179586f : dd;
+                    out[s] = make_float4(csy * dx + sny * dy, -sny * dx + csy * dy, dd,
+                                         (float)((unsigned)bits >> 24));
                     oidx[s] = bits & 0xffffff;
                 } else if (s >= nsel && s < K) {
                     out[s] = make_float4(0.f, 0.f, 0.f, 0.f);
