@@ -152,6 +152,24 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
     return v;
 }
 
+// Concatenated row spans (lane r < nrows holds row r's span as [end - len, end) of the
+// concatenation and delta = first point - (end - len)): the point at position b + lane,
+// for a chunk start b below the total.  r is the first row that ends after the previous
+// chunk's start and is advanced; the rows that start inside the chunk are applied in order.
+__device__ __forceinline__ int span_point(int b, int lane, int end, int off, int delta,
+                                          int nrows, int &r) {
+    while (__builtin_amdgcn_readlane(end, r) <= b) r++;
+    const int p = b + lane;
+    int q = p + __builtin_amdgcn_readlane(delta, r);
+    for (int rr = r + 1; rr < nrows; rr++) {
+        const int o = __builtin_amdgcn_readlane(off, rr);
+        if (o >= b + 64) break;
+        const int d = __builtin_amdgcn_readlane(delta, rr);
+        q = p >= o ? p + d : q;
+    }
+    return q;
+}
+
 __host__ __device__ inline int stage_cap(int K) { return ((K + 64 + 63) / 64) * 64; }
 
 // Point indices and packed (bin, point) candidates: 16-bit / 32-bit when every world has
@@ -391,21 +409,32 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
                 const int cx1 = cell_coord(xi + ex + m, g.ox, g.inv_cs, g.nx);
                 const int cy0 = cell_coord(yi - ey - m, g.oy, g.inv_cs, g.ny);
                 const int cy1 = cell_coord(yi + ey + m, g.oy, g.inv_cs, g.ny);
+                // the cells' segment ranges of each row, concatenated (lane = row), so that
+                // the segments of all rows fill the lanes together
+                const int nre = cy1 - cy0 + 1;  // at most kGridAxis
+                int e0 = 0, e1 = 0;
+                if (lane < nre) {
+                    e0 = ecs[(cy0 + lane) * g.nx + cx0];
+                    e1 = ecs[(cy0 + lane) * g.nx + cx1 + 1];
+                }
+                const int elen = e1 - e0;
+                const int eend = wave_incl_scan(elen);
+                const int EM = __builtin_amdgcn_readlane(eend, kWave - 1);
+                const int eoff = eend - elen;
+                const int edel = e0 - eoff;
                 bool hit = false;
-                for (int cy = cy0; cy <= cy1 && !hit; cy++) {
-                    const int q0 = ecs[cy * g.nx + cx0], q1 = ecs[cy * g.nx + cx1 + 1];
-                    for (int base = q0; base < q1 && !hit; base += kWave) {
-                        const int q = base + lane;
-                        bool h = false;
-                        if (q < q1) {
-                            const float4 e = es[q];
-                            const float x0 = e.x - xi, y0 = e.y - yi, x1 = e.z - xi, y1 = e.w - yi;
-                            if (!(fminf(x0, x1) > ex || fmaxf(x0, x1) < -ex || fminf(y0, y1) > ey ||
-                                  fmaxf(y0, y1) < -ey))
-                                h = sat_box_seg(ci, si, hL, hW, x0, y0, x1, y1) < 0.0f;
-                        }
-                        hit = __ballot(h) != 0ull;
+                int er = 0;
+                for (int base = 0; base < EM && !hit; base += kWave) {
+                    const int q = span_point(base, lane, eend, eoff, edel, nre, er);
+                    bool h = false;
+                    if (base + lane < EM) {
+                        const float4 e = es[q];
+                        const float x0 = e.x - xi, y0 = e.y - yi, x1 = e.z - xi, y1 = e.w - yi;
+                        if (!(fminf(x0, x1) > ex || fmaxf(x0, x1) < -ex || fminf(y0, y1) > ey ||
+                              fmaxf(y0, y1) < -ey))
+                            h = sat_box_seg(ci, si, hL, hW, x0, y0, x1, y1) < 0.0f;
                     }
+                    hit = __ballot(h) != 0ull;
                 }
                 if (lane == 0)
                     scoll[i] = (agent_hit ? (int)GD_FLAG_COLL_AGENT : 0) | (hit ? (int)GD_FLAG_COLL_EDGE : 0);
@@ -615,18 +644,7 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             int r = 0;  // the first row that ends after the current chunk's start
             // point of this lane's position in the chunk starting at b (< M): the row
             // that holds position b, then the later rows that start inside the chunk
-            auto chunk_point = [&](int b) {
-                while (__builtin_amdgcn_readlane(end, r) <= b) r++;
-                const int p = b + lane;
-                int q = p + __builtin_amdgcn_readlane(delta, r);
-                for (int rr = r + 1; rr < nrows; rr++) {
-                    const int o = __builtin_amdgcn_readlane(off, rr);
-                    if (o >= b + kWave) break;
-                    const int d = __builtin_amdgcn_readlane(delta, rr);
-                    q = p >= o ? p + d : q;
-                }
-                return q;
-            };
+            auto chunk_point = [&](int b) { return span_point(b, lane, end, off, delta, nrows, r); };
             for (int base = 0; base < M; base += SU * kWave) {
                 int qv[SU];
                 float2 pt[SU];
