@@ -164,10 +164,11 @@ static long long partner_slots_of(const gd_config *c, const int32_t *h_agent_off
 // Launch shape of the step kernel: waves per workgroup, distance bins, candidate-list
 // entries per wave, and whether the road is staged in LDS.  Fields the config fixes are
 // kept; the rest maximise resident waves per compute unit (counting only the workgroups
-// the batch can fill), then the number of resident workgroups, then prefer 512 bins, a candidate list of at least 512 entries
-// (the smallest such), and staged edge segments.  GD_ROAD_AUTO stages the road when that
-// keeps as many resident waves as reading it through the caches (the road then costs no
-// memory round trips in the observation phase), else reads it through the caches.
+// the batch can fill), then the number of resident workgroups, then a candidate list of
+// at least 512 entries (the smallest such), then 512 bins, then staged edge segments.
+// GD_ROAD_AUTO stages the road when that keeps as many resident waves as reading it
+// through the caches (the road then costs no memory round trips in the observation
+// phase), else reads it through the caches.
 struct Shape {
     long score = -1;
     int waves = 0, bins = 0, cand_cap = 0, edge_cap = 0, road_cap = 0, resident = 0;
@@ -200,7 +201,7 @@ static Shape best_shape(const gd_config *c, bool staged, int max_road, int cell_
                     // waves, whose world phases then overlap other workgroups' observation
                     // phases (smaller workgroups serialise too many agents per wave)
                     const long score = (long)wgs * wv * 10000 + (wv >= 8 ? wgs * 200 : 0) +
-                                       bin_pref(nb) * 20 + cand_pref(cc) * 4 + (ec ? 1 : 0);
+                                       cand_pref(cc) * 20 + bin_pref(nb) * 4 + (ec ? 1 : 0);
                     if (score > best.score) {
                         best.score = score;
                         best.waves = wv;
