@@ -12,16 +12,16 @@
 // radius range + longest segment, then the four sides of every other visible agent within
 // range.  Each candidate is moved into the ego frame; those whose closest point lies
 // within range are compacted into a per-wave list, and the list is processed with one
-// candidate per lane: the arc it subtends gives the (few) rays it can meet, widened by one
-// ray on each side, and each of those rays is intersected exactly; a per-ray 64-bit LDS
-// minimum over (distance bits, type) keeps the nearest hit (ties: road edge first).
+// candidate per lane: the arc it subtends (widened by 1 mrad) gives the few rays it can
+// meet, and each of those rays is intersected exactly; a per-ray 64-bit LDS minimum over
+// (distance bits, type) keeps the nearest hit (ties: road edge first).
 #include "gd_internal.h"
 
 namespace gdk {
 
 // Angle of (x, y) in [-pi, pi] within 2e-5 rad.  It only selects which rays a candidate
-// is tested against, a range widened by one ray on each side, so any error well below the
-// ray spacing (2 pi / N >= 6e-3 rad) leaves the hits unchanged.  atan(a) on [0, 1] is
+// is tested against, a range widened by 1 mrad on each side, so it leaves the hits
+// unchanged.  atan(a) on [0, 1] is
 // a * P(a^2) with P a degree-4 least-squares fit on Chebyshev nodes (max error 1.2e-5).
 __device__ __forceinline__ float ray_angle(float y, float x) {
     const float ax = fabsf(x), ay = fabsf(y);
@@ -49,10 +49,13 @@ __device__ __forceinline__ void lidar_candidate(float ax, float ay, float bx, fl
         lo = pb;
         span = -span;
     }
-    // rays k with angle 2 pi k / N inside [lo, lo + span], widened by one ray each side
-    int k0 = (int)floorf(lo * inv_step) - 1;
-    int k1 = (int)ceilf((lo + span) * inv_step) + 1;
-    if (k1 - k0 >= N) {
+    // rays k with angle 2 pi k / N inside [lo, lo + span] widened by 1 mrad on each side
+    // (far above the angle error, below any ray spacing); an arc within 0.01 rad of pi
+    // (the segment passes next to the origin, where the rounded angles could pick the
+    // complementary arc) takes every ray
+    int k0 = (int)ceilf((lo - 1e-3f) * inv_step);
+    int k1 = (int)floorf((lo + span + 1e-3f) * inv_step);
+    if (k1 - k0 >= N - 1 || span > 3.13159265f) {
         k0 = 0;
         k1 = N - 1;
     }

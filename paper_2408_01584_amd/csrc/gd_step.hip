@@ -780,14 +780,15 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             const int b = bin_of(k, bscale, NB);
             const int lo = b > 0 ? hist[b - 1] : 0;
             const int hi = hist[b];
-            int rank = 0;
-            int tie = 0;
+            // mates with a smaller key, and with a smaller or equal one (itself included):
+            // a difference above 1 means an exact key tie
+            int rank = 0, rank_le = 0;
             for (int m = lo; m < hi; m++) {
                 const float ko = skey[m];
                 rank += (int)(ko < k);
-                tie |= (int)(ko == k) & (int)(m != p);
+                rank_le += (int)(ko <= k);
             }
-            if (tie) {
+            if (rank_le - rank > 1) {
                 const int my_idx = __float_as_int(aux[q].y) & 0xffffff;
                 for (int m = lo; m < hi; m++)
                     if (m != p && skey[m] == k)
