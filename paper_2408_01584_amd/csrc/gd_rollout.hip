@@ -1,6 +1,7 @@
 // Differentiable rollout: forward with checkpoints and backward by recomputation.
 //
-// Forward: one thread per agent runs T bicycle steps (App. B) and after each step the
+// Forward: a group of 16 lanes per agent runs T bicycle steps (App. B; computed alike by
+// the 16 lanes, which share the nearest-edge search) and after each step the
 // smooth reward  r = -|g'| - softplus(s),  g' = R(-yaw)(g - p),  s = signed distance (in
 // the ego frame, positive on the right of the segment direction, i.e. off-road) to the
 // nearest road-edge segment within the observation radius (s = -R when there is none).
@@ -16,7 +17,9 @@
 
 namespace gdk {
 
-constexpr int kRollThreads = 64;
+constexpr int kRollThreads = 64;                // threads per workgroup
+constexpr int kGroup = 16;                      // lanes per agent (one DPP row)
+constexpr int kRollAgents = kRollThreads / kGroup;
 constexpr int kMaxCkpt = 32;
 
 struct EdgeChoice {
@@ -24,26 +27,48 @@ struct EdgeChoice {
     float side;     // +1 off-road (right of the segment direction), -1 on-road
 };
 
+// Lane groups: 16 lanes (one DPP row) work on one agent.  Minimum over the group of
+// (distance bits, world-local index) with the cell-sorted position carried along, by row
+// rotations (every lane ends with the group minimum).
+__device__ __forceinline__ void group_min(unsigned &hi, unsigned &lo, int &q) {
+#define GD_ROR_STEP(ctrl)                                                                   \
+    {                                                                                      \
+        const unsigned h2 = (unsigned)__builtin_amdgcn_update_dpp(0, (int)hi, ctrl, 0xf, 0xf, false); \
+        const unsigned l2 = (unsigned)__builtin_amdgcn_update_dpp(0, (int)lo, ctrl, 0xf, 0xf, false); \
+        const int q2 = __builtin_amdgcn_update_dpp(0, q, ctrl, 0xf, 0xf, false);           \
+        const bool less = h2 < hi || (h2 == hi && l2 < lo);                                \
+        hi = less ? h2 : hi;                                                               \
+        lo = less ? l2 : lo;                                                               \
+        q = less ? q2 : q;                                                                 \
+    }
+    GD_ROR_STEP(0x128)  // row_ror:8
+    GD_ROR_STEP(0x124)  // row_ror:4
+    GD_ROR_STEP(0x122)  // row_ror:2
+    GD_ROR_STEP(0x121)  // row_ror:1
+#undef GD_ROR_STEP
+}
+
 // nearest road-edge segment to (px, py) within R (ties -> lowest world-local index), by
-// rings of grid cells around the point's cell.  Segments are keyed by the cell of their
+// rings of grid cells around the point's cell, searched by the 16 lanes of a group (`sub`
+// = lane within the group; each cell's segments are spread over them).  Segments are keyed by the cell of their
 // first point, so a segment at distance d has its key within d + max_seg.  A key in a cell
 // r rings out is at least (r - 1) * cs away, so before ring r is searched every unseen
 // segment is at least (r - 1) * cs - max_seg away, and the search stops once that exceeds
 // the best distance found (or the radius).
-__device__ EdgeChoice nearest_edge(const WorldGrid &g, const int *ecs, const float4 *es,
-                                   const int *eid, float px, float py, float R) {
+__device__ EdgeChoice nearest_edge16(const WorldGrid &g, const int *ecs, const float4 *es,
+                                     const int *eid, float px, float py, float R, int sub) {
     EdgeChoice ch{-1, -1.0f};
     if (g.n_edge == 0 || !(px == px) || !(py == py)) return ch;
     const float fx = floorf((px - g.ox) * g.inv_cs), fy = floorf((py - g.oy) * g.inv_cs);
-    // the point's (unclamped) cell, kept in a range where the ring loop stays short
     const int cx = (int)fminf(fmaxf(fx, -1.0e6f), 1.0e6f);
     const int cy = (int)fminf(fmaxf(fy, -1.0e6f), 1.0e6f);
     const int rmax = (int)ceilf((R + g.max_seg) * g.inv_cs) + 1;
-    float best = INFINITY;
-    int bestk = 0x7fffffff;
+    unsigned bhi = 0x7f800000u, blo = 0xffffffffu;  // (+inf, no index)
+    int bq = -1;
     for (int r = 0; r <= rmax; r++) {
+        group_min(bhi, blo, bq);
+        const float best = __uint_as_float(bhi);
         if (best <= R && best + g.max_seg + 1e-3f * g.cs < (float)(r - 1) * g.cs) break;
-        // ring r: rows cy-r .. cy+r; full rows at the top and bottom, two cells otherwise
         const int y0 = max(cy - r, 0), y1 = min(cy + r, g.ny - 1);
         for (int yy = y0; yy <= y1; yy++) {
             const bool edge_row = (yy == cy - r) || (yy == cy + r);
@@ -59,7 +84,7 @@ __device__ EdgeChoice nearest_edge(const WorldGrid &g, const int *ecs, const flo
                 }
                 if (x0 > x1) continue;
                 const int q0 = ecs[yy * g.nx + x0], q1 = ecs[yy * g.nx + x1 + 1];
-                for (int q = q0; q < q1; q++) {
+                for (int q = q0 + sub; q < q1; q += 16) {
                     const float4 e = es[q];
                     const float ex = e.z - e.x, ey = e.w - e.y;
                     const float ax = e.x - px, ay = e.y - py;
@@ -68,21 +93,20 @@ __device__ EdgeChoice nearest_edge(const WorldGrid &g, const int *ecs, const flo
                     u = fminf(fmaxf(u, 0.0f), 1.0f);
                     const float qx = ax + u * ex, qy = ay + u * ey;
                     const float d = sqrtf(qx * qx + qy * qy);
-                    const int k = eid[q];
-                    if (d < best || (d == best && k < bestk)) {
-                        best = d;
-                        bestk = k;
-                        ch.q = q;
+                    const unsigned dh = __float_as_uint(d), k = (unsigned)eid[q];
+                    if (dh < bhi || (dh == bhi && k < blo)) {
+                        bhi = dh;
+                        blo = k;
+                        bq = q;
                     }
                 }
             }
         }
     }
-    if (!(best <= R)) {
-        ch.q = -1;
-        return ch;
-    }
-    const float4 e = es[ch.q];
+    group_min(bhi, blo, bq);
+    if (!(__uint_as_float(bhi) <= R) || bq < 0) return ch;
+    ch.q = bq;
+    const float4 e = es[bq];
     const float cr = (e.z - e.x) * (py - e.y) - (e.w - e.y) * (px - e.x);
     ch.side = cr < 0.0f ? 1.0f : -1.0f;
     return ch;
@@ -142,7 +166,10 @@ __device__ __forceinline__ void world_of(const int *agent_off, int W, int i, int
 __global__ __launch_bounds__(kRollThreads) void k_rollout_fwd(SimArgs a, const float2 *__restrict__ act,
                                                               int T, int C, float *__restrict__ rewards,
                                                               float *__restrict__ ckpt) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // 16 lanes per agent: the nearest-edge search is spread over them, the rest of the
+    // step is computed by all 16 alike and written by the first
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gid / kGroup, sub = gid % kGroup;
     if (i >= a.A) return;
     int w;
     world_of(a.agent_off, a.W, i, w);
@@ -155,7 +182,7 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_fwd(SimArgs a, const f
     const float L = a.len[i], gx = a.gx[i], gy = a.gy[i];
     const size_t A = (size_t)a.A;
     for (int t = 0; t < T; t++) {
-        if (t % C == 0) {
+        if (t % C == 0 && sub == 0) {
             float *ck = ckpt + (size_t)(t / C) * 4 * A;
             ck[i] = x;
             ck[A + i] = y;
@@ -164,8 +191,9 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_fwd(SimArgs a, const f
         }
         const float2 u = act[(size_t)t * A + i];
         bicycle_r(x, y, yaw, v, L, u.x, u.y, a.dt, a.vmax);
-        const EdgeChoice ch = nearest_edge(g, ecs, es, eid, x, y, a.R_obs);
-        rewards[(size_t)t * A + i] = smooth_reward(x, y, yaw, gx, gy, es, ch, a.R_obs);
+        const EdgeChoice ch = nearest_edge16(g, ecs, es, eid, x, y, a.R_obs, sub);
+        const float rw = smooth_reward(x, y, yaw, gx, gy, es, ch, a.R_obs);
+        if (sub == 0) rewards[(size_t)t * A + i] = rw;
     }
 }
 
@@ -176,15 +204,18 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_bwd(SimArgs a, const f
                                                               float *__restrict__ grad_s0) {
     // per thread: states before steps c0..c0+C (C+1 entries) and the segment choice of the
     // reward after each of the C steps
-    __shared__ float4 s_state[kRollThreads * (kMaxCkpt + 1)];
-    __shared__ int s_q[kRollThreads * kMaxCkpt];
-    __shared__ float s_side[kRollThreads * kMaxCkpt];
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    // (16 lanes per agent as in the forward kernel; the per-agent LDS records are written
+    // by the group's first lane and read by all 16)
+    __shared__ float4 s_state[kRollAgents * (kMaxCkpt + 1)];
+    __shared__ int s_q[kRollAgents * kMaxCkpt];
+    __shared__ float s_side[kRollAgents * kMaxCkpt];
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = gid / kGroup, sub = gid % kGroup;
     if (i >= a.A) return;
-    const int tid = threadIdx.x;
-    float4 *st = s_state + tid * (kMaxCkpt + 1);
-    int *sq = s_q + tid * kMaxCkpt;
-    float *ss = s_side + tid * kMaxCkpt;
+    const int la = threadIdx.x / kGroup;
+    float4 *st = s_state + la * (kMaxCkpt + 1);
+    int *sq = s_q + la * kMaxCkpt;
+    float *ss = s_side + la * kMaxCkpt;
     int w;
     world_of(a.agent_off, a.W, i, w);
     const WorldGrid g = a.grid[w];
@@ -203,15 +234,21 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_bwd(SimArgs a, const f
         // recompute the segment forward
         const float *ck = ckpt + (size_t)sgi * 4 * A;
         float x = ck[i], y = ck[A + i], yaw = ck[2 * A + i], v = ck[3 * A + i];
-        st[0] = make_float4(x, y, yaw, v);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (sub == 0) st[0] = make_float4(x, y, yaw, v);
         for (int t = c0; t < c1; t++) {
             const float2 u = act[(size_t)t * A + i];
             bicycle_r(x, y, yaw, v, L, u.x, u.y, dt, vmax);
-            st[t - c0 + 1] = make_float4(x, y, yaw, v);
-            const EdgeChoice ch = nearest_edge(g, ecs, es, eid, x, y, a.R_obs);
-            sq[t - c0] = ch.q;
-            ss[t - c0] = ch.side;
+            const EdgeChoice ch = nearest_edge16(g, ecs, es, eid, x, y, a.R_obs, sub);
+            if (sub == 0) {
+                st[t - c0 + 1] = make_float4(x, y, yaw, v);
+                sq[t - c0] = ch.q;
+                ss[t - c0] = ch.side;
+            }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
         // reverse
         for (int t = c1 - 1; t >= c0; t--) {
             const float gr = grad_r[(size_t)t * A + i];
@@ -291,12 +328,12 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_bwd(SimArgs a, const f
             const float bdl = lth * vb * cb * sec2 / L * dt + bbeta * dbeta;
             const float bv = bvb * c1f + lv * c2f;
             const float ba = bvb * c1f * 0.5f * dt + lv * c2f * dt;
-            grad_a[(size_t)t * A + i] = make_float2(ba, bdl);
+            if (sub == 0) grad_a[(size_t)t * A + i] = make_float2(ba, bdl);
             lth = bth;
             lv = bv;
         }
     }
-    if (grad_s0) {
+    if (grad_s0 && sub == 0) {
         grad_s0[i] = lx;
         grad_s0[A + i] = ly;
         grad_s0[2 * A + i] = lth;
@@ -307,7 +344,7 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_bwd(SimArgs a, const f
 hipError_t launch_rollout_fwd_impl(const SimArgs &a, const float2 *actions, int T, int C,
                                    float *rewards, float *ckpt, hipStream_t s) {
     if (C < 1 || C > kMaxCkpt) return hipErrorInvalidValue;
-    const int blocks = (a.A + kRollThreads - 1) / kRollThreads;
+    const int blocks = (int)(((long long)a.A * kGroup + kRollThreads - 1) / kRollThreads);
     hipLaunchKernelGGL(k_rollout_fwd, dim3(blocks), dim3(kRollThreads), 0, s, a, actions, T, C, rewards, ckpt);
     return hipGetLastError();
 }
@@ -316,7 +353,7 @@ hipError_t launch_rollout_bwd_impl(const SimArgs &a, const float2 *actions, cons
                                    int C, const float *grad_rewards, float2 *grad_actions,
                                    float *grad_state0, hipStream_t s) {
     if (C < 1 || C > kMaxCkpt) return hipErrorInvalidValue;
-    const int blocks = (a.A + kRollThreads - 1) / kRollThreads;
+    const int blocks = (int)(((long long)a.A * kGroup + kRollThreads - 1) / kRollThreads);
     hipLaunchKernelGGL(k_rollout_bwd, dim3(blocks), dim3(kRollThreads), 0, s, a, actions, ckpt, T, C,
                        grad_rewards, grad_actions, grad_state0);
     return hipGetLastError();
