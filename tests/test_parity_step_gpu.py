@@ -94,3 +94,25 @@ def test_graph_mode_bitwise_equal(gpu):
         b = gr.host_outputs()
         for n in ("state", "flags", "reward", "world_done", "t"):
             assert np.array_equal(a[n], b[n]), (k, n)
+
+
+def test_autotuner_picks_a_listed_shape_with_the_same_bits(gpu, tmp_path, monkeypatch):
+    """tune.autotune times the given launch shapes on the device and returns the fastest;
+    the simulator at that shape gives the same bits as the library default."""
+    from paper_2408_01584_amd import scenes as S, tune
+    import torch
+    monkeypatch.setattr(tune, "CACHE", str(tmp_path / "tuned.json"))
+    sc = S.make_scene(2, worlds=[0, 1, 2, 3])
+    space = [dict(obs_waves=8, obs_bins=256, obs_cands=512, cell_size=12.0, obs_road=2),
+             dict(obs_waves=16, obs_bins=512, obs_cands=512, cell_size=15.0, obs_road=2)]
+    best = tune.autotune(sc, space=space, steps=4, warmup=1, use_cache=True)
+    assert best in space
+    assert tune.autotune(sc, space=space, steps=4, warmup=1, use_cache=True) == best  # cached
+    acts = torch.as_tensor(S.make_actions(2, 3, sc.num_agents), device="cuda")
+    ref, alt = _sim(sc), _sim(sc, **best)
+    for k in range(3):
+        ref.step(acts[k])
+        alt.step(acts[k])
+    a, b = ref.host_outputs(), alt.host_outputs()
+    for key in a:
+        assert np.array_equal(a[key], b[key]), key
