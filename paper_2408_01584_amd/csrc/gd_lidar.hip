@@ -224,26 +224,40 @@ __global__ __launch_bounds__(kLidarMaxWaves * kWave) void k_lidar(SimArgs a, Lid
             }
             nl += cnt;
         };
-        // road-edge segments keyed in the rows that meet the disc of radius `reach`
+        // road-edge segments keyed in the rows that meet the disc of radius `reach`: one
+        // lane per row computes the row's range of cell-sorted segments, and the ranges
+        // are concatenated so that the segments of all rows fill the lanes together
         if (g.n_edge > 0) {
             const int rlo = cell_coord(py - reach, g.oy, g.inv_cs, g.ny);
             const int rhi = cell_coord(py + reach, g.oy, g.inv_cs, g.ny);
-            for (int r = rlo; r <= rhi; r++) {
+            const int nrw = rhi - rlo + 1;  // at most kGridAxis
+            int q0 = 0, q1 = 0;
+            if (lane < nrw) {
+                const int r = rlo + lane;
                 const float ylo = g.oy + (float)r * g.cs, yhi = ylo + g.cs;
                 const float dy = fmaxf(fmaxf(ylo - py, py - yhi), 0.0f);
-                if (dy > reach) continue;
-                const float hw = sqrtf(fmaxf(reach * reach - dy * dy, 0.0f)) + 1e-3f * g.cs;
-                const int c0 = cell_coord(px - hw, g.ox, g.inv_cs, g.nx);
-                const int c1 = cell_coord(px + hw, g.ox, g.inv_cs, g.nx);
-                const int q0 = ecs[r * g.nx + c0], q1 = ecs[r * g.nx + c1 + 1];
-                for (int base = q0; base < q1; base += kWave) {
-                    const int q = base + lane;
-                    const float4 e = es[q < q1 ? q : q0];
-                    const float dx0 = e.x - px, dy0 = e.y - py, dx1 = e.z - px, dy1 = e.w - py;
-                    const float ax = cs * dx0 + sn * dy0, ay = -sn * dx0 + cs * dy0;
-                    const float bx = cs * dx1 + sn * dy1, by = -sn * dx1 + cs * dy1;
-                    push(q < q1 && seg_in_range(ax, ay, bx, by, r2c), ax, ay, bx, by, 1u);
+                if (dy <= reach) {
+                    const float hw = sqrtf(fmaxf(reach * reach - dy * dy, 0.0f)) + 1e-3f * g.cs;
+                    const int c0 = cell_coord(px - hw, g.ox, g.inv_cs, g.nx);
+                    const int c1 = cell_coord(px + hw, g.ox, g.inv_cs, g.nx);
+                    q0 = ecs[r * g.nx + c0];
+                    q1 = ecs[r * g.nx + c1 + 1];
                 }
+            }
+            const int len = q1 - q0;
+            const int end = wave_incl_scan(len);
+            const int M = __builtin_amdgcn_readlane(end, kWave - 1);
+            const int off = end - len;
+            const int del = q0 - off;
+            int rr = 0;
+            for (int base = 0; base < M; base += kWave) {
+                const int q = span_point(base, lane, end, off, del, nrw, rr);
+                const bool ok = base + lane < M;
+                const float4 e = es[ok ? q : 0];
+                const float dx0 = e.x - px, dy0 = e.y - py, dx1 = e.z - px, dy1 = e.w - py;
+                const float ax = cs * dx0 + sn * dy0, ay = -sn * dx0 + cs * dy0;
+                const float bx = cs * dx1 + sn * dy1, by = -sn * dx1 + cs * dy1;
+                push(ok && seg_in_range(ax, ay, bx, by, r2c), ax, ay, bx, by, 1u);
             }
         }
         // sides of the other visible agents' boxes

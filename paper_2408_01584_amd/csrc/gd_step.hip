@@ -139,37 +139,6 @@ __device__ __forceinline__ float wave_uniform(float v) {
 }
 __device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// Inclusive prefix sum over the 64 lanes with DPP moves: shifts by 1, 2, 4, 8 inside each
-// row of 16 lanes, then the last lane of row 0 (2) added to row 1 (3), then lane 31 added
-// to rows 2 and 3.  Lanes whose DPP source is out of range or whose row is masked add 0.
-__device__ __forceinline__ int wave_incl_scan(int v) {
-    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false);  // row_shr:1
-    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false);  // row_shr:2
-    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false);  // row_shr:4
-    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false);  // row_shr:8
-    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
-    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
-    return v;
-}
-
-// Concatenated row spans (lane r < nrows holds row r's span as [end - len, end) of the
-// concatenation and delta = first point - (end - len)): the point at position b + lane,
-// for a chunk start b below the total.  r is the first row that ends after the previous
-// chunk's start and is advanced; the rows that start inside the chunk are applied in order.
-__device__ __forceinline__ int span_point(int b, int lane, int end, int off, int delta,
-                                          int nrows, int &r) {
-    while (__builtin_amdgcn_readlane(end, r) <= b) r++;
-    const int p = b + lane;
-    int q = p + __builtin_amdgcn_readlane(delta, r);
-    for (int rr = r + 1; rr < nrows; rr++) {
-        const int o = __builtin_amdgcn_readlane(off, rr);
-        if (o >= b + 64) break;
-        const int d = __builtin_amdgcn_readlane(delta, rr);
-        q = p >= o ? p + d : q;
-    }
-    return q;
-}
-
 __host__ __device__ inline int stage_cap(int K) { return ((K + 64 + 63) / 64) * 64; }
 
 // Point indices and packed (bin, point) candidates: 16-bit / 32-bit when every world has
