@@ -100,7 +100,7 @@ __device__ __forceinline__ bool seg_in_range(float ax, float ay, float bx, float
 
 // LDS layout of one workgroup (byte offsets, 16-aligned regions)
 struct LidarLds {
-    size_t dirs, best, list, ltype, agents, edges, ecells, total;
+    size_t dirs, best, list, ltype, nearl, agents, edges, ecells, total;
 };
 
 __host__ __device__ inline LidarLds lidar_layout(int N, int waves, int agent_cap, int edge_cap,
@@ -111,7 +111,8 @@ __host__ __device__ inline LidarLds lidar_layout(int N, int waves, int agent_cap
     L.best = up((size_t)N * 8);
     L.list = L.best + up((size_t)waves * N * 8);
     L.ltype = L.list + (size_t)waves * kLidarList * 16;
-    L.agents = L.ltype + up((size_t)waves * kLidarList);
+    L.nearl = L.ltype + up((size_t)waves * kLidarList);
+    L.agents = L.nearl + up((size_t)waves * agent_cap * 2);
     // x, y, cos, sin, half length, half width, half diagonal, flags
     L.edges = L.agents + up((size_t)agent_cap * 4 * 8);
     L.ecells = L.edges + (size_t)edge_cap * 16;
@@ -130,6 +131,7 @@ __global__ __launch_bounds__(kLidarMaxWaves * kWave) void k_lidar(SimArgs a, Lid
     unsigned long long *best = reinterpret_cast<unsigned long long *>(smem + L.best) + (size_t)wid * N;
     float4 *lst = reinterpret_cast<float4 *>(smem + L.list) + (size_t)wid * kLidarList;
     unsigned char *ltype = smem + L.ltype + (size_t)wid * kLidarList;
+    unsigned short *nearl = reinterpret_cast<unsigned short *>(smem + L.nearl) + (size_t)wid * lc.agent_cap;
     const int ac = lc.agent_cap;
     float *sx = reinterpret_cast<float *>(smem + L.agents);
     float *sy = sx + ac, *sc = sx + 2 * ac, *ss = sx + 3 * ac, *shl = sx + 4 * ac,
@@ -260,28 +262,42 @@ __global__ __launch_bounds__(kLidarMaxWaves * kWave) void k_lidar(SimArgs a, Lid
                 push(ok && seg_in_range(ax, ay, bx, by, r2c), ax, ay, bx, by, 1u);
             }
         }
-        // sides of the other visible agents' boxes
+        // sides of the other visible agents' boxes: the agents near enough are compacted
+        // first, then one lane per (agent, side)
+        int nnear = 0;
         for (int jb = 0; jb < n; jb += kWave) {
             const int j = jb + lane;
             const int jj = j < n ? j : 0;
             const float dxj = sx[jj] - px, dyj = sy[jj] - py;
             const float rr = range + sdg[jj] + 1e-3f;
             const bool near = j < n && j != l && (sf[jj] & GD_FLAG_VISIBLE) && dxj * dxj + dyj * dyj <= rr * rr;
-            const float cj = sc[jj], sj = ss[jj], hl = shl[jj], hw = shw[jj];
+            const unsigned long long bal = __ballot(near);
+            if (near)
+                nearl[nnear + __builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u))] =
+                    (unsigned short)j;
+            nnear += __popcll(bal);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int tb = 0; tb < 4 * nnear; tb += kWave) {
+            const int tt = tb + lane;
+            const bool ok = tt < 4 * nnear;
+            const int j = nearl[ok ? tt >> 2 : 0];
+            const int side = tt & 3;
+            const float dxj = sx[j] - px, dyj = sy[j] - py;
+            const float cj = sc[j], sj = ss[j], hl = shl[j], hw = shw[j];
             // corners (+hl,+hw) (+hl,-hw) (-hl,-hw) (-hl,+hw); side k joins corner k and k+1
-#pragma unroll
-            for (int side = 0; side < 4; side++) {
-                const float ax0 = (side == 0 || side == 1) ? hl : -hl;
-                const float ay0 = (side == 0 || side == 3) ? hw : -hw;
-                const int side1 = (side + 1) & 3;
-                const float ax1 = (side1 == 0 || side1 == 1) ? hl : -hl;
-                const float ay1 = (side1 == 0 || side1 == 3) ? hw : -hw;
-                const float ux0 = dxj + cj * ax0 - sj * ay0, uy0 = dyj + sj * ax0 + cj * ay0;
-                const float ux1 = dxj + cj * ax1 - sj * ay1, uy1 = dyj + sj * ax1 + cj * ay1;
-                const float ax = cs * ux0 + sn * uy0, ay = -sn * ux0 + cs * uy0;
-                const float bx = cs * ux1 + sn * uy1, by = -sn * ux1 + cs * uy1;
-                push(near && seg_in_range(ax, ay, bx, by, r2c), ax, ay, bx, by, 2u);
-            }
+            const int side1 = (side + 1) & 3;
+            const float ax0 = (side == 0 || side == 1) ? hl : -hl;
+            const float ay0 = (side == 0 || side == 3) ? hw : -hw;
+            const float ax1 = (side1 == 0 || side1 == 1) ? hl : -hl;
+            const float ay1 = (side1 == 0 || side1 == 3) ? hw : -hw;
+            const float ux0 = dxj + cj * ax0 - sj * ay0, uy0 = dyj + sj * ax0 + cj * ay0;
+            const float ux1 = dxj + cj * ax1 - sj * ay1, uy1 = dyj + sj * ax1 + cj * ay1;
+            const float ax = cs * ux0 + sn * uy0, ay = -sn * ux0 + cs * uy0;
+            const float bx = cs * ux1 + sn * uy1, by = -sn * ux1 + cs * uy1;
+            push(ok && seg_in_range(ax, ay, bx, by, r2c), ax, ay, bx, by, 2u);
         }
         flush();
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
