@@ -178,6 +178,7 @@ template <int NB, int RM>
 __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_next_agent;  // phase 5 work counter
+    __shared__ int s_next_coll;   // phase 2 work counter
     int *s_next = &s_next_agent;
     constexpr bool STAGED = RM == kRoadLds;
     constexpr bool IDX16 = RM != kRoadGlobal32;
@@ -228,6 +229,7 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
 
     const WorldGrid g = a.grid[w];
     const int ncell = g.nx * g.ny;
+    if (tid == 0) s_next_coll = 0;  // published by the barrier that ends phase 1
     // phases 0 and 1 share one memory round trip: each thread issues the loads of its
     // first agent and of its share of the staging copies before its first LDS store
     int t = a.t[w];
@@ -354,7 +356,13 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
         {
             const int *ecs = c.edge_cap ? secells : a.ecell_start + (size_t)w * kCellStride;
             const float4 *es = c.edge_cap ? sedge : a.eseg + r0;
-            for (int i = wid; i < n; i += nwaves) {
+            // each wave starts with agent `wid`, then takes the next unclaimed one
+            auto next_coll = [&]() {
+                int v = 0;
+                if (lane == 0) v = atomicAdd(&s_next_coll, 1);
+                return nwaves + __builtin_amdgcn_readfirstlane(v);
+            };
+            for (int i = wid; i < n; i = next_coll()) {
                 if (!(wave_uniform(sf[i]) & GD_FLAG_ALIVE)) continue;
                 const float xi = wave_uniform(sx[i]), yi = wave_uniform(sy[i]);
                 const float ci = wave_uniform(sc[i]), si = wave_uniform(ss[i]);
