@@ -161,3 +161,28 @@ def test_nonfinite_action_reported(gpu):
     sim.check()  # cleared
     g = sim.host_outputs()
     assert np.isnan(g["state"][0, 3]) and (g["road_idx"][3] == -1).all()
+
+
+def test_large_world_32bit_point_indices(gpu, oracle_mod):
+    """A world of 70 000 road points (more than 16-bit point indices hold) takes the kernel
+    variant with 32-bit indices and the road read through the caches; the agents sit in the
+    last of 140 copies of the 500-point scene, so their top-K indices exceed 65535."""
+    from paper_2408_01584_amd import scenes as S
+    base = S.make_scene(0)
+    tiles = 140
+    offs = [(1000.0 * (k % 12), 1000.0 * (k // 12)) for k in range(tiles)]
+    sc = base.copy()
+    sc.road_x = np.concatenate([base.road_x + ox for ox, _ in offs]).astype(base.road_x.dtype)
+    sc.road_y = np.concatenate([base.road_y + oy for _, oy in offs]).astype(base.road_y.dtype)
+    sc.road_dir = np.tile(base.road_dir, tiles)
+    sc.road_meta = np.tile(base.road_meta, tiles)
+    sc.road_off = np.array([0, base.num_road * tiles], np.int32)
+    ox, oy = offs[-1]
+    for name, o in (("x", ox), ("goal_x", ox), ("y", oy), ("goal_y", oy)):
+        setattr(sc, name, (getattr(base, name) + o).astype(getattr(base, name).dtype))
+    acts = S.make_actions(0, 3, sc.num_agents)
+    sim = _sim(sc)
+    st = teacher_forced_run(sc, sim, oracle_mod, acts, 3)
+    g = sim.host_outputs()
+    assert g["road_idx"].max() >= 65536
+    print("70 000-point world:", st)
