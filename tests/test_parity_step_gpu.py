@@ -35,6 +35,33 @@ def test_cfg1_subset(gpu, oracle_mod):
     print("cfg1 4 worlds:", st)
 
 
+def test_cfg1_full_size_bench_shape(gpu, oracle_mod):
+    """The whole headline workload (256 worlds x 64 agents, 4000 points, K 200, 63
+    partners) at the launch shape the benchmark times, teacher-forced against the oracle
+    on every world for a few steps, after warm-up steps that put the pruned search radius
+    in use."""
+    from paper_2408_01584_amd import scenes as S
+    import torch
+    sc = S.make_scene(1)
+    acts = S.make_actions(1, 8, sc.num_agents)
+    sim = _sim(sc)
+    for k in range(5):
+        sim.step(torch.as_tensor(acts[k], device="cuda"))
+    st = teacher_forced_run(sc, sim, oracle_mod, acts[5:], 3)
+    print("cfg1 all 256 worlds:", st)
+
+
+def test_cfg3_full_size(gpu, oracle_mod):
+    """The whole rollout workload's step (512 worlds x 32 agents, 2000 points, K 64, 31
+    partners) against the oracle on every world."""
+    from paper_2408_01584_amd import scenes as S
+    sc = S.make_scene(3)
+    acts = S.make_actions(3, 3, sc.num_agents)
+    sim = _sim(sc)
+    st = teacher_forced_run(sc, sim, oracle_mod, acts, 3)
+    print("cfg3 all 512 worlds:", st)
+
+
 def test_cfg2_uneven_subset(gpu, oracle_mod):
     """Uneven worlds (agent counts, road sizes) with a ragged partner layout."""
     from paper_2408_01584_amd import scenes as S
