@@ -8,6 +8,9 @@
  * What it computes (GPUDrive, arXiv 2408.01584):
  *   - kinematic bicycle model about the centre of gravity, l_r = L/2, midpoint speed
  *     clipped to +-v_max, explicit Euler                          (App. B, all equations)
+ *   - the simplified, invertible bicycle model (a double integrator along the heading
+ *     with the yaw update of Sec. 3.2 "Dynamics") and its inversion: the actions that
+ *     carry one logged state to the next                          (Sec. 3.2 "Dynamics")
  *   - agent/agent and agent/road-edge collision of convex boxes and edge segments
  *                                        (Sec. 3.1; Sec. 3.2 "Termination", "Sharp edges")
  *   - goal reached within a configurable distance, reward 1 (+ optional collision
@@ -58,7 +61,15 @@ typedef struct {
     int32_t top_k, partners, episode_len, lidar_rays;
     uint32_t flags;
     double dt, obs_radius, goal_radius, v_max, lidar_range, collision_penalty;
+    int32_t model; /* OR_MODEL_BICYCLE or OR_MODEL_DELTA */
 } or_config;
+
+#define OR_MODEL_BICYCLE 0
+#define OR_MODEL_DELTA 1
+
+/* the inversion leaves the steering at zero when a step covers less than this distance
+   (m): the yaw change of such a step cannot be reproduced by a finite command */
+#define OR_INV_MIN_DIST 1e-3
 
 typedef struct {
     int32_t W;
@@ -147,6 +158,68 @@ void or_dynamics(int n, double *x, double *y, double *yaw, double *v, const doub
         if (alive && !alive[i]) continue;
         or_dynamics_one(&x[i], &y[i], &yaw[i], &v[i], len[i], actions[2 * i], actions[2 * i + 1],
                         dt, vmax);
+    }
+}
+
+/* ------------------------------------------------------------------ simplified model (Sec. 3.2)
+
+   Position and speed follow a double integrator along the current heading, and the yaw
+   turns by the steering command times the distance covered in the step:
+       d = v dt + a dt^2 / 2,  x += d cos(yaw),  y += d sin(yaw),  yaw += s d,  v += a dt.
+   The command s is a curvature (1/m).  Neither the speed nor the actions are clipped
+   (the model is invertible only for unbounded actions), and the vehicle length plays no
+   part. */
+void or_delta_one(double *x, double *y, double *yaw, double *v, double a, double s, double dt) {
+    double d = *v * dt + 0.5 * a * dt * dt;
+    double th = *yaw;
+    *x += d * cos(th);
+    *y += d * sin(th);
+    *yaw = th + s * d;
+    *v += a * dt;
+}
+
+void or_delta(int n, double *x, double *y, double *yaw, double *v, const double *actions,
+              const uint8_t *alive, double dt) {
+    for (int i = 0; i < n; i++) {
+        if (alive && !alive[i]) continue;
+        or_delta_one(&x[i], &y[i], &yaw[i], &v[i], actions[2 * i], actions[2 * i + 1], dt);
+    }
+}
+
+/* one step of the configured model */
+static void move_one(const or_config *c, double *x, double *y, double *yaw, double *v, double L,
+                     double a, double u) {
+    if (c->model == OR_MODEL_DELTA) or_delta_one(x, y, yaw, v, a, u, c->dt);
+    else or_dynamics_one(x, y, yaw, v, L, a, u, c->dt, c->v_max);
+}
+
+/* Inversion of the simplified model: from consecutive states (yaw, speed) of a log,
+   states[(t*4 + q)*n + i] with q = (x, y, yaw, speed) for t = 0..T, the actions that
+   reproduce the speed and the yaw of every step exactly:
+       a = (v1 - v0) / dt,   d = (v0 + v1) dt / 2,   s = wrap(yaw1 - yaw0) / d,
+   with s = 0 when |d| < OR_INV_MIN_DIST.  The yaw difference is wrapped to [-pi, pi) so
+   that logs with wrapped headings invert to the same command.  Positions are reproduced
+   when the log itself follows the model.  band[(t*n + i)] (optional) gets 1 where |d| is
+   within 1e-9 m of the threshold or the yaw difference within 1e-9 rad of +-pi. */
+void or_delta_invert(int n, int T, const double *states, double dt, double *actions,
+                     uint8_t *band) {
+    for (int t = 0; t < T; t++) {
+        const double *s0 = states + (int64_t)t * 4 * n, *s1 = s0 + (int64_t)4 * n;
+        for (int i = 0; i < n; i++) {
+            double v0 = s0[3 * n + i], v1 = s1[3 * n + i];
+            double dth = s1[2 * n + i] - s0[2 * n + i];
+            double a = (v1 - v0) / dt;
+            double d = v0 * dt + 0.5 * a * dt * dt;
+            double w = wrap_angle(dth);
+            double st = fabs(d) < OR_INV_MIN_DIST ? 0.0 : w / d;
+            actions[((int64_t)t * n + i) * 2] = a;
+            actions[((int64_t)t * n + i) * 2 + 1] = st;
+            if (band) {
+                int near = fabs(fabs(d) - OR_INV_MIN_DIST) < 1e-9 ||
+                           fabs(fabs(w) - OR_PI) < 1e-9 || fabs(fabs(dth) - OR_PI) < 1e-9;
+                band[(int64_t)t * n + i] = (uint8_t)near;
+            }
+        }
     }
 }
 
@@ -476,8 +549,8 @@ static void step_world(const or_batch *b, const or_config *c, int w, const doubl
     /* 1. dynamics of the alive agents */
     for (int i = a0; i < a1; i++) {
         if (!(b->flags[i] & OR_ALIVE)) continue;
-        or_dynamics_one(&b->x[i], &b->y[i], &b->yaw[i], &b->v[i], b->len[i], actions[2 * i],
-                        actions[2 * i + 1], c->dt, c->v_max);
+        move_one(c, &b->x[i], &b->y[i], &b->yaw[i], &b->v[i], b->len[i], actions[2 * i],
+                 actions[2 * i + 1]);
     }
     /* 2-3. agent/agent and agent/edge collision on the post-dynamics state */
     collide_world(b, w, coll, o->band);
@@ -671,8 +744,9 @@ void or_rollout(const or_batch *b, const or_config *c, int T, const double *acti
             for (int t = 0; t < T; t++) {
                 double a = actions[((int64_t)t * A + i) * 2], dl = actions[((int64_t)t * A + i) * 2 + 1];
                 double vb = v + 0.5 * a * c->dt, vn = v + a * c->dt;
-                if (fabs(fabs(vb) - c->v_max) < tol || fabs(fabs(vn) - c->v_max) < tol) un = 1;
-                or_dynamics_one(&x, &y, &th, &v, b->len[i], a, dl, c->dt, c->v_max);
+                if (c->model == OR_MODEL_BICYCLE &&
+                    (fabs(fabs(vb) - c->v_max) < tol || fabs(fabs(vn) - c->v_max) < tol)) un = 1;
+                move_one(c, &x, &y, &th, &v, b->len[i], a, dl);
                 seg_choice sc = nearest_edge(b, c, w, x, y);
                 if (sc.seg >= 0) sc.side = side_of(b, sc.seg, x, y);
                 int cl = 0;
@@ -717,7 +791,7 @@ void or_rollout_vjp(const or_batch *b, const or_config *c, int T, const double *
             for (int t = 0; t < T; t++) {
                 double x = S[4 * t], y = S[4 * t + 1], th = S[4 * t + 2], v = S[4 * t + 3];
                 double a = actions[((int64_t)t * A + i) * 2], dl = actions[((int64_t)t * A + i) * 2 + 1];
-                or_dynamics_one(&x, &y, &th, &v, L, a, dl, dt, c->v_max);
+                move_one(c, &x, &y, &th, &v, L, a, dl);
                 S[4 * (t + 1)] = x; S[4 * (t + 1) + 1] = y; S[4 * (t + 1) + 2] = th; S[4 * (t + 1) + 3] = v;
                 SC[t] = nearest_edge(b, c, w, x, y);
                 if (SC[t].seg >= 0) SC[t].side = side_of(b, SC[t].seg, x, y);
@@ -783,6 +857,18 @@ void or_rollout_vjp(const or_batch *b, const or_config *c, int T, const double *
                 double x0 = S[4 * t], y0 = S[4 * t + 1], th0 = S[4 * t + 2], v0 = S[4 * t + 3];
                 (void)x0; (void)y0;
                 double a = actions[((int64_t)t * A + i) * 2], dl = actions[((int64_t)t * A + i) * 2 + 1];
+                if (c->model == OR_MODEL_DELTA) {
+                    /* d = v dt + a dt^2/2; x += d cos th; y += d sin th; th += s d; v += a dt */
+                    double d = v0 * dt + 0.5 * a * dt * dt;
+                    double ct0 = cos(th0), st0 = sin(th0);
+                    double bd = lx * ct0 + ly * st0 + lth * dl;
+                    double bth = lth + d * (-lx * st0 + ly * ct0);
+                    grad_actions[((int64_t)t * A + i) * 2] = lv * dt + bd * 0.5 * dt * dt;
+                    grad_actions[((int64_t)t * A + i) * 2 + 1] = lth * d;
+                    lth = bth;
+                    lv = lv + bd * dt;
+                    continue;
+                }
                 double vb_raw = v0 + 0.5 * a * dt;
                 double vb = clipd(vb_raw, -c->v_max, c->v_max);
                 double c1 = (vb_raw > -c->v_max && vb_raw < c->v_max) ? 1.0 : 0.0;

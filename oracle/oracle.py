@@ -21,6 +21,8 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 COLL_AGENT, COLL_EDGE, GOAL, DONE, ALIVE, VISIBLE = 1, 2, 4, 8, 16, 32
 AUTO_RESET, TERM_ON_COLLISION = 1, 2
+MODEL_BICYCLE, MODEL_DELTA = 0, 1
+INV_MIN_DIST = 1e-3  # the inversion's distance threshold (m), as in gd_oracle.c
 
 
 def build(force: bool = True) -> str:
@@ -49,7 +51,8 @@ class Config(C.Structure):
     _fields_ = [("top_k", C.c_int32), ("partners", C.c_int32), ("episode_len", C.c_int32),
                 ("lidar_rays", C.c_int32), ("flags", C.c_uint32), ("dt", C.c_double),
                 ("obs_radius", C.c_double), ("goal_radius", C.c_double), ("v_max", C.c_double),
-                ("lidar_range", C.c_double), ("collision_penalty", C.c_double)]
+                ("lidar_range", C.c_double), ("collision_penalty", C.c_double),
+                ("model", C.c_int32)]
 
 
 class Batch(C.Structure):
@@ -67,6 +70,8 @@ class Outputs(C.Structure):
 def _declare(L):
     vp, i32, d = C.c_void_p, C.c_int, C.c_double
     L.or_dynamics.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, d, d]
+    L.or_delta.argtypes = [i32, vp, vp, vp, vp, vp, vp, d]
+    L.or_delta_invert.argtypes = [i32, i32, vp, d, vp, vp]
     L.or_box_box_sep.argtypes = [vp, vp]
     L.or_box_box_sep.restype = d
     L.or_box_seg_sep.argtypes = [vp, d, d, d, d]
@@ -88,7 +93,8 @@ def _p(a):
 def config_from_params(p) -> Config:
     flags = (AUTO_RESET if p.auto_reset else 0) | (TERM_ON_COLLISION if p.terminate_on_collision else 0)
     return Config(p.top_k, p.partners, p.episode_len, p.lidar_rays, flags, p.dt, p.obs_radius,
-                  p.goal_radius, p.v_max, p.lidar_range, p.collision_penalty)
+                  p.goal_radius, p.v_max, p.lidar_range, p.collision_penalty,
+                  getattr(p, "dynamics", MODEL_BICYCLE))
 
 
 def partner_slots(agent_off: np.ndarray, partners: int) -> int:
@@ -106,6 +112,28 @@ def dynamics(x, y, yaw, v, length, actions, dt=0.1, v_max=30.0, alive=None):
     al = None if alive is None else np.ascontiguousarray(alive, dtype=np.uint8)
     lib().or_dynamics(len(x), _p(x), _p(y), _p(yaw), _p(v), _p(length), _p(act), _p(al), dt, v_max)
     return x, y, yaw, v
+
+
+def delta_dynamics(x, y, yaw, v, actions, dt=0.1, alive=None):
+    """One step of the simplified bicycle model (Sec. 3.2 "Dynamics") in FP64: actions are
+    (acceleration m/s^2, curvature command 1/m); returns new arrays."""
+    x, y, yaw, v = (np.array(a, dtype=np.float64, copy=True) for a in (x, y, yaw, v))
+    act = np.ascontiguousarray(actions, dtype=np.float64).reshape(-1, 2)
+    al = None if alive is None else np.ascontiguousarray(alive, dtype=np.uint8)
+    lib().or_delta(len(x), _p(x), _p(y), _p(yaw), _p(v), _p(act), _p(al), dt)
+    return x, y, yaw, v
+
+
+def invert_actions(states, dt=0.1):
+    """Actions [T, n, 2] of the simplified model that carry states[t] to states[t+1]
+    (states [T+1, 4, n]: x, y, yaw, speed), and a band mask [T, n] of the steps whose
+    command sits at a decision threshold (see ``or_delta_invert``)."""
+    st = np.ascontiguousarray(states, dtype=np.float64)
+    T, n = st.shape[0] - 1, st.shape[2]
+    act = np.zeros((max(T, 0), n, 2))
+    band = np.zeros((max(T, 0), n), np.uint8)
+    lib().or_delta_invert(n, T, _p(st), dt, _p(act), _p(band))
+    return act, band
 
 
 def box_box_sep(a, b) -> float:

@@ -64,6 +64,7 @@ class SimParams:
     collision_penalty: float = 0.0
     auto_reset: bool = True
     terminate_on_collision: bool = False
+    dynamics: int = 0  # 0: bicycle model (App. B); 1: simplified model (Sec. 3.2 "Dynamics")
 
 
 @dataclass(frozen=True)
@@ -372,6 +373,16 @@ def assemble(cfg, parts, params: SimParams, world_ids=None) -> Scene:
                  goal_y=cat("goal_y"), road_x=cat("road_x"), road_y=cat("road_y"),
                  road_dir=cat("road_dir"), road_meta=cat("road_meta", np.int32),
                  extra={"world_ids": list(world_ids) if world_ids is not None else None})
+
+
+def make_delta_actions(cfg: int, steps: int, num_agents: int) -> np.ndarray:
+    """float32 [steps, num_agents, 2] for the simplified model: (accel U(-3,2) m/s^2,
+    curvature command U(-0.06,0.06) 1/m, i.e. turning radii of 17 m and more), drawn from
+    SeedSequence(3000 + cfg)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(3000 + cfg)))
+    acc = rng.uniform(-3.0, 2.0, size=(steps, num_agents))
+    curv = rng.uniform(-0.06, 0.06, size=(steps, num_agents))
+    return np.ascontiguousarray(np.stack([acc, curv], axis=-1).astype(np.float32))
 
 
 def make_actions(cfg: int, steps: int, num_agents: int) -> np.ndarray:
