@@ -199,8 +199,9 @@ static void move_one(const or_config *c, double *x, double *y, double *yaw, doub
        a = (v1 - v0) / dt,   d = (v0 + v1) dt / 2,   s = wrap(yaw1 - yaw0) / d,
    with s = 0 when |d| < OR_INV_MIN_DIST.  The yaw difference is wrapped to [-pi, pi) so
    that logs with wrapped headings invert to the same command.  Positions are reproduced
-   when the log itself follows the model.  band[(t*n + i)] (optional) gets 1 where |d| is
-   within 1e-9 m of the threshold or the yaw difference within 1e-9 rad of +-pi. */
+   when the log itself follows the model.  band[(t*n + i)] (optional) gets 1 where the
+   two decisions are not determined at binary32 precision: |d| within 1e-8 m of the
+   threshold, or the yaw difference within 1e-5 rad of +-pi. */
 void or_delta_invert(int n, int T, const double *states, double dt, double *actions,
                      uint8_t *band) {
     for (int t = 0; t < T; t++) {
@@ -215,8 +216,8 @@ void or_delta_invert(int n, int T, const double *states, double dt, double *acti
             actions[((int64_t)t * n + i) * 2] = a;
             actions[((int64_t)t * n + i) * 2 + 1] = st;
             if (band) {
-                int near = fabs(fabs(d) - OR_INV_MIN_DIST) < 1e-9 ||
-                           fabs(fabs(w) - OR_PI) < 1e-9 || fabs(fabs(dth) - OR_PI) < 1e-9;
+                int near = fabs(fabs(d) - OR_INV_MIN_DIST) < 1e-8 ||
+                           fabs(fabs(w) - OR_PI) < 1e-5 || fabs(fabs(dth) - OR_PI) < 1e-5;
                 band[(int64_t)t * n + i] = (uint8_t)near;
             }
         }
