@@ -250,7 +250,8 @@ def secondary(args):
     """Secondary workloads: config 0 (one world, launch latency), 2 (1024 uneven worlds,
     direct launches against a HIP graph per step), 3 (512 x 32, T = 20: step, and the
     differentiable rollout forward against forward + backward) and 4 (4096 x 64 with
-    30-ray LIDAR, T = 91 rollout with checkpoints every 10 steps).  Median of 5 repeats."""
+    30-ray LIDAR, T = 91 rollout with checkpoints every 10 steps); for 3 and 4 also the
+    simplified model's step and its action inversion.  Median of 5 repeats."""
     import torch
 
     from paper_2408_01584_amd import scenes as S
@@ -318,7 +319,53 @@ def secondary(args):
             "checkpoint_bytes_every_step": int(T * 4 * A * 4),
             "peak_extra_bytes_fwd_bwd": int(peak_ck)}
         sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        out["delta"] = delta_model_legs(scene, T, c)
     print(json.dumps(out), flush=True)
+
+
+def delta_model_legs(scene, T, c):
+    """The simplified (invertible) bicycle model on the same workload: the full step with
+    it, and the expert-action inversion of a T-step log of every agent (one launch, HBM
+    bound: reads heading and speed of T+1 states, writes T actions, 16 B per agent-step)."""
+    import dataclasses
+
+    import torch
+
+    from paper_2408_01584_amd import gd as G
+    from paper_2408_01584_amd import scenes as S
+    from paper_2408_01584_amd.sim import Sim
+
+    A = scene.num_agents
+    acts = torch.as_tensor(S.make_delta_actions(c, T + 10, A), device="cuda")
+    sim = Sim(scene, params=dataclasses.replace(scene.params, dynamics=G.GD_DYN_DELTA))
+
+    def steps(n):
+        def f():
+            for k in range(n):
+                sim.step(acts[k])
+        return f
+    steps(10)()
+    ms = _timed(steps(T))
+    _, log = sim.rollout_fwd(acts[:T + 1].contiguous(), 1)  # [T+1, 4, A]
+    inv = torch.empty((T, A, 2), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    reps = 20
+
+    def invert():
+        for _ in range(reps):
+            G.gd_invert_actions(sim.handle, log.data_ptr(), T, inv.data_ptr(), stream)
+    invert()
+    ms_inv = _timed(invert) / reps
+    nbytes = A * ((T + 1) * 8 + T * 8)
+    gbs = nbytes / (ms_inv * 1e-3) / 1e9
+    sim.close()
+    return {"step_ms": round(ms / T, 5), "step_agent_steps_per_s": round(A * T / (ms / 1e3), 1),
+            "invert": {"T": T, "ms_per_launch": round(ms_inv, 5),
+                       "agent_steps_per_s": round(A * T / (ms_inv / 1e3), 1),
+                       "algorithmic_bytes_per_launch": nbytes, "achieved_GBps": round(gbs, 1),
+                       "hbm_frac": round(gbs * 1e9 / HBM_PEAK, 4)}}
 
 
 def cpu_baseline(cfg_id, steps):

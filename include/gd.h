@@ -6,7 +6,9 @@
  *   - many independent worlds, each with its own number of agents, stepped together on
  *     one accelerator, memory proportional to the instantiated agents   (Sec. 3.1)
  *   - road map as polylines of typed points                     (Sec. 3.1, Sec. 3.2 "Dataset")
- *   - kinematic bicycle dynamics driven by (acceleration, steering)   (Sec. 3.2, App. B)
+ *   - kinematic bicycle dynamics driven by (acceleration, steering)   (Sec. 3.2, App. B),
+ *     or the simplified invertible model and its expert-action inversion
+ *                                                            (Sec. 3.2 "Dynamics")
  *   - collision of convex boxes with each other and with road edges
  *                                       (Sec. 3.1; Sec. 3.2 "Termination", "Sharp edges")
  *   - radius-filter observations in the agent's relative frame; planar LIDAR
@@ -81,6 +83,11 @@ typedef enum {
 #define GD_ROAD_LDS 1
 #define GD_ROAD_GLOBAL 2
 
+/* gd_config.dynamics */
+#define GD_DYN_BICYCLE 0  /* kinematic bicycle model (App. B); actions (accel, steer rad) */
+#define GD_DYN_DELTA 1    /* simplified, invertible model (Sec. 3.2 "Dynamics"); actions
+                             (accel, curvature command 1/m) */
+
 #define GD_MAX_AGENTS_PER_WORLD 1024
 #define GD_MAX_ROAD_PER_WORLD (1 << 24)
 #define GD_MAX_TOP_K 960
@@ -116,7 +123,7 @@ typedef struct {
                                   16 B per point of the largest world), GD_ROAD_GLOBAL
                                   (from the workspace through the caches) or GD_ROAD_AUTO
                                   (staged when that keeps as many resident waves) */
-    int32_t reserved;          /* must be zero */
+    int32_t dynamics;          /* GD_DYN_BICYCLE or GD_DYN_DELTA */
 } gd_config;
 
 typedef struct {
@@ -171,10 +178,13 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off,
 gd_status gd_reset(gd_sim *sim, const uint8_t *world_mask, void *stream);
 
 /* One full step for all worlds (Sec. 3.2; App. B):
- *   1. alive agents move by the bicycle model with actions [A,2] = (accel m/s^2,
- *      steer rad): vbar = clip(v + a dt/2, +-v_max), beta = atan(tan(steer)/2),
- *      x += vbar cos(yaw + beta) dt, y += vbar sin(yaw + beta) dt,
- *      yaw += vbar cos(beta) tan(steer) / length dt, v = clip(v + a dt, +-v_max);
+ *   1. alive agents move by the configured model.  GD_DYN_BICYCLE (App. B), actions
+ *      [A,2] = (accel m/s^2, steer rad): vbar = clip(v + a dt/2, +-v_max),
+ *      beta = atan(tan(steer)/2), x += vbar cos(yaw + beta) dt,
+ *      y += vbar sin(yaw + beta) dt, yaw += vbar cos(beta) tan(steer) / length dt,
+ *      v = clip(v + a dt, +-v_max).  GD_DYN_DELTA (Sec. 3.2 "Dynamics"), actions
+ *      (accel m/s^2, curvature command s 1/m): d = v dt + a dt^2/2, x += d cos(yaw),
+ *      y += d sin(yaw), yaw += s d, v += a dt (no clip, independent of the length);
  *   2. collision flags among alive agents (oriented boxes) and against road-edge
  *      segments, on the new state;
  *   3. goal (|p - g| <= goal_radius), reward = [goal] - penalty [collided], done =
@@ -203,7 +213,8 @@ gd_status gd_step(gd_sim *sim, const float *actions, void *stream);
 gd_status gd_obs(gd_sim *sim, void *stream);
 
 /* Differentiable rollout (forward).  Starting from the current state (the state buffers
- * are not modified), runs T bicycle steps for every agent -- no collision, done or reset
+ * are not modified), runs T steps of the configured model (gd_step, step 1) for every
+ * agent -- no collision, done or reset
  * -- with actions [T,A,2], and writes the smooth reward after each step
  *     rewards[t,i] = -|g' | - softplus(s)
  * where g' = R(-yaw)(g - p) is the goal in the ego frame and s is the signed distance, in
@@ -227,6 +238,20 @@ gd_status gd_rollout_bwd(gd_sim *sim, const float *actions, const float *ckpt, i
                          int32_t ckpt_every, const float *grad_rewards, float *grad_actions,
                          float *grad_state0, void *stream);
 
+/* Expert-action inversion for the simplified model (Sec. 3.2 "Dynamics": the model is
+ * invertible for unbounded actions, which makes logged trajectories usable as
+ * demonstrations).  states [T+1,4,A] (x, y, yaw, speed per step, device, the layout of
+ * the rollout checkpoints) -> actions [T,A,2] (device) with, for each step t,
+ *     a = (v[t+1] - v[t]) / dt,   d = (v[t] + v[t+1]) dt / 2,
+ *     s = wrap(yaw[t+1] - yaw[t]) / d   (0 when |d| < 1 mm; wrap to [-pi, pi)),
+ * so that gd_step / gd_rollout_fwd with these actions reproduce each step's speed and
+ * heading (positions too when the log follows the model).  Computed in binary32.
+ * Requires cfg.dynamics == GD_DYN_DELTA (GD_E_ARG otherwise).  0 <= T <= 1048560
+ * (GD_E_SIZE above); states and
+ * actions must not overlap.  Asynchronous on `stream`. */
+gd_status gd_invert_actions(gd_sim *sim, const float *states, int32_t T, float *actions,
+                            void *stream);
+
 /* Re-point the observation outputs (obs_ego, obs_partner, partner_mask, obs_road,
  * road_idx, lidar, lidar_hit; the other fields of `bufs` are ignored) so that the next
  * calls write the observation straight into, e.g., step t of a caller's rollout buffer.
@@ -244,7 +269,8 @@ gd_status gd_set_obs_buffers(gd_sim *sim, const gd_buffers *bufs);
 #define GD_PHASE_LIDAR 1
 #define GD_PHASE_ROLLOUT_FWD 2
 #define GD_PHASE_ROLLOUT_BWD 3
-#define GD_NUM_PHASES 4
+#define GD_PHASE_INVERT 4
+#define GD_NUM_PHASES 5
 gd_status gd_set_timing(gd_sim *sim, int32_t enable);
 gd_status gd_get_timing(gd_sim *sim, double *ms, int64_t *count);
 

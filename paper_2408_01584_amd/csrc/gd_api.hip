@@ -21,6 +21,9 @@ hipError_t launch_rollout_fwd_impl(const SimArgs &a, const float2 *actions, int 
 hipError_t launch_rollout_bwd_impl(const SimArgs &a, const float2 *actions, const float *ckpt,
                                    int T, int C, const float *grad_rewards, float2 *grad_actions,
                                    float *grad_state0, hipStream_t s);
+hipError_t launch_invert_actions_impl(const float *states, int T, int A, float dt, float *actions,
+                                      hipStream_t s);
+constexpr int kMaxInvertSteps = 65535 * 16;  // launch chunks of 16 steps on grid axis y
 bool step_kernel_node(const SimArgs *a, const StepCtl *c, int waves, int bins,
                       hipKernelNodeParams &p, void **args);
 bool lidar_kernel_node(const SimArgs *a, const LidarCtl *lc, hipKernelNodeParams &p, void **args);
@@ -137,7 +140,8 @@ static gd_status check_config(const gd_config *c, const int32_t *h_agent_off,
         return fail(GD_E_ARG, "obs_cands must be 0, 128, 256, 384, 512, 768 or 1024");
     if (!(c->obs_road == GD_ROAD_AUTO || c->obs_road == GD_ROAD_LDS || c->obs_road == GD_ROAD_GLOBAL))
         return fail(GD_E_ARG, "obs_road must be GD_ROAD_AUTO, GD_ROAD_LDS or GD_ROAD_GLOBAL");
-    if (c->reserved) return fail(GD_E_ARG, "reserved field must be zero");
+    if (!(c->dynamics == GD_DYN_BICYCLE || c->dynamics == GD_DYN_DELTA))
+        return fail(GD_E_ARG, "dynamics must be GD_DYN_BICYCLE or GD_DYN_DELTA");
     const int W = c->num_worlds;
     if (h_agent_off[0] != 0 || h_road_off[0] != 0) return fail(GD_E_ARG, "offsets must start at 0");
     for (int w = 0; w < W; w++) {
@@ -415,6 +419,7 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
     a.N = cfg->lidar_rays;
     a.T_ep = cfg->episode_len;
     a.flags = cfg->flags;
+    a.dyn = cfg->dynamics;
     a.dt = cfg->dt;
     a.R_obs = cfg->obs_radius;
     {
@@ -599,6 +604,24 @@ gd_status gd_rollout_bwd(gd_sim *sim, const float *actions, const float *ckpt, i
           launch_rollout_bwd_impl(sim->args, (const float2 *)actions, ckpt, T, ckpt_every, grad_rewards,
                                   (float2 *)grad_actions, grad_state0, s),
           "rollout backward launch");
+    return GD_OK;
+}
+
+gd_status gd_invert_actions(gd_sim *sim, const float *states, int32_t T, float *actions, void *stream) {
+    if (!sim) return fail(GD_E_ARG, "sim is NULL");
+    if (sim->cfg.dynamics != GD_DYN_DELTA)
+        return fail(GD_E_ARG, "action inversion needs the simplified model (GD_DYN_DELTA)");
+    if (T < 0) return fail(GD_E_ARG, "T must be >= 0");
+    if (T > kMaxInvertSteps) return fail(GD_E_SIZE, "T = %d exceeds %d", T, kMaxInvertSteps);
+    const int A = sim->args.A;
+    if (T == 0 || A == 0) return GD_OK;
+    if (!states || !actions) return fail(GD_E_ARG, "NULL buffer");
+    const char *s0 = (const char *)states, *s1 = s0 + (size_t)(T + 1) * 4 * A * sizeof(float);
+    const char *a0 = (const char *)actions, *a1 = a0 + (size_t)T * 2 * A * sizeof(float);
+    if (a0 < s1 && s0 < a1) return fail(GD_E_ARG, "states and actions overlap");
+    hipStream_t s = (hipStream_t)stream;
+    TIMED(sim, s, GD_PHASE_INVERT, launch_invert_actions_impl(states, T, A, sim->args.dt, actions, s),
+          "action inversion launch");
     return GD_OK;
 }
 

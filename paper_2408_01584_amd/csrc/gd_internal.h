@@ -30,6 +30,7 @@ struct SimArgs {
     int W, A, R;
     int K, P, N, T_ep;
     uint32_t flags;
+    int dyn;  // GD_DYN_BICYCLE or GD_DYN_DELTA
     float dt, R_obs, R2_obs, goal_r2, vmax, lidar_range, penalty;
 
     // caller buffers
@@ -130,6 +131,20 @@ __device__ __forceinline__ float wrap_pi(float a) {
     if (r >= 3.14159265358979323846f) r -= two_pi;
     if (r < -3.14159265358979323846f) r += two_pi;
     return r;
+}
+
+// Simplified bicycle model (Sec. 3.2 "Dynamics"): a double integrator along the heading
+// held during the step, the yaw turning by the command s (1/m) times the distance covered.
+// No clip, no dependence on the vehicle length.
+__device__ __forceinline__ void delta_model(float &x, float &y, float &yaw, float &v, float acc,
+                                            float s, float dt) {
+    const float d = v * dt + 0.5f * acc * dt * dt;
+    float sn, cs;
+    sincosf(yaw, &sn, &cs);
+    x = x + d * cs;
+    y = y + d * sn;
+    yaw = yaw + s * d;
+    v = v + acc * dt;
 }
 
 // Cell of coordinate v on an axis of n cells (clamped; NaN maps to cell 0).  Monotone

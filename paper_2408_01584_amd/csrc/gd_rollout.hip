@@ -190,7 +190,8 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_fwd(SimArgs a, const f
             ck[3 * A + i] = v;
         }
         const float2 u = act[(size_t)t * A + i];
-        bicycle_r(x, y, yaw, v, L, u.x, u.y, a.dt, a.vmax);
+        if (a.dyn == GD_DYN_DELTA) delta_model(x, y, yaw, v, u.x, u.y, a.dt);
+        else bicycle_r(x, y, yaw, v, L, u.x, u.y, a.dt, a.vmax);
         const EdgeChoice ch = nearest_edge16(g, ecs, es, eid, x, y, a.R_obs, sub);
         const float rw = smooth_reward(x, y, yaw, gx, gy, es, ch, a.R_obs);
         if (sub == 0) rewards[(size_t)t * A + i] = rw;
@@ -239,7 +240,8 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_bwd(SimArgs a, const f
         if (sub == 0) st[0] = make_float4(x, y, yaw, v);
         for (int t = c0; t < c1; t++) {
             const float2 u = act[(size_t)t * A + i];
-            bicycle_r(x, y, yaw, v, L, u.x, u.y, dt, vmax);
+            if (a.dyn == GD_DYN_DELTA) delta_model(x, y, yaw, v, u.x, u.y, dt);
+            else bicycle_r(x, y, yaw, v, L, u.x, u.y, dt, vmax);
             const EdgeChoice ch = nearest_edge16(g, ecs, es, eid, x, y, a.R_obs, sub);
             if (sub == 0) {
                 st[t - c0 + 1] = make_float4(x, y, yaw, v);
@@ -310,6 +312,17 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_bwd(SimArgs a, const f
             // dynamics s_t -> s_{t+1}
             const float4 s0 = st[t - c0];
             const float2 u = act[(size_t)t * A + i];
+            if (a.dyn == GD_DYN_DELTA) {
+                // d = v dt + a dt^2/2; x += d cos(yaw); y += d sin(yaw); yaw += s d; v += a dt
+                const float d = s0.w * dt + 0.5f * u.x * dt * dt;
+                float sn0, cs0;
+                sincosf(s0.z, &sn0, &cs0);
+                const float bd = lx * cs0 + ly * sn0 + lth * u.y;
+                if (sub == 0) grad_a[(size_t)t * A + i] = make_float2(lv * dt + bd * 0.5f * dt * dt, lth * d);
+                lth = lth + d * (ly * cs0 - lx * sn0);
+                lv = lv + bd * dt;
+                continue;
+            }
             const float vb_raw = s0.w + 0.5f * u.x * dt;
             const float vb = fminf(fmaxf(vb_raw, -vmax), vmax);
             const float c1f = (vb_raw > -vmax && vb_raw < vmax) ? 1.0f : 0.0f;
@@ -339,6 +352,73 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_bwd(SimArgs a, const f
         grad_s0[2 * A + i] = lth;
         grad_s0[3 * A + i] = lv;
     }
+}
+
+// Heading difference y1 - y0 wrapped to [-pi, pi), rounded once: the difference is kept
+// as an unevaluated sum (two-sum, no multiplication involved), the multiple of 2 pi is
+// removed with 2 pi split into a binary32 head (subtracted exactly) and tail.  A plain
+// binary32 wrap of a log whose heading crosses +-pi would carry an absolute error of a
+// few 1e-7 rad into the curvature command, divided by the distance of the step.
+__device__ __forceinline__ float wrap_diff(float y1, float y0) {
+    const float two_pi_hi = 6.28318548202514648f;   // binary32 nearest to 2 pi
+    const float two_pi_lo = -1.74845553e-07f;       // 2 pi - two_pi_hi
+    const float inv_two_pi = 0.159154943091895336f;
+    const float pi_f = 3.14159265358979324f;
+    const float a = y1 - y0;
+    const float bb = a - y1;
+    const float err = (y1 - (a - bb)) + (-y0 - bb);
+    const float k = floorf((a + pi_f) * inv_two_pi);
+    float r = fmaf(-k, two_pi_hi, a);
+    r = r + (err - k * two_pi_lo);
+    if (r >= pi_f) r = (r - two_pi_hi) - two_pi_lo;
+    if (r < -pi_f) r = (r + two_pi_hi) + two_pi_lo;
+    return r;
+}
+
+// Expert-action inversion of the simplified model: one thread per agent and chunk of
+// kInvChunk steps, all of the chunk's (yaw, speed) rows loaded before any action is
+// formed.  Row t0 + kInvChunk is read by two chunks.
+constexpr int kInvThreads = 256;
+constexpr int kInvChunk = 16;
+
+__global__ __launch_bounds__(kInvThreads) void k_invert_actions(const float *__restrict__ st, int T, int A,
+                                                                float dt, float2 *__restrict__ act) {
+    const int i = blockIdx.x * kInvThreads + threadIdx.x;
+    if (i >= A) return;
+    const size_t As = (size_t)A;
+    const int t0 = blockIdx.y * kInvChunk;
+    float yw[kInvChunk + 1], vv[kInvChunk + 1];
+#pragma unroll
+    for (int k = 0; k <= kInvChunk; k++) {
+        const int t = t0 + k;
+        yw[k] = 0.f;
+        vv[k] = 0.f;
+        if (t <= T) {
+            const float *row = st + (size_t)t * 4 * As;
+            yw[k] = row[2 * As + i];
+            vv[k] = row[3 * As + i];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kInvChunk; k++) {
+        const int t = t0 + k;
+        if (t < T) {
+            const float acc = (vv[k + 1] - vv[k]) / dt;
+            const float d = 0.5f * (vv[k] + vv[k + 1]) * dt;
+            const float w = wrap_diff(yw[k + 1], yw[k]);
+            const float s = fabsf(d) < 1e-3f ? 0.0f : w / d;
+            act[(size_t)t * As + i] = make_float2(acc, s);
+        }
+    }
+}
+
+hipError_t launch_invert_actions_impl(const float *states, int T, int A, float dt, float *actions,
+                                      hipStream_t s) {
+    const int chunks = (T + kInvChunk - 1) / kInvChunk;
+    if (chunks > 65535) return hipErrorInvalidValue;
+    const dim3 grid((A + kInvThreads - 1) / kInvThreads, chunks);
+    hipLaunchKernelGGL(k_invert_actions, grid, dim3(kInvThreads), 0, s, states, T, A, dt, (float2 *)actions);
+    return hipGetLastError();
 }
 
 hipError_t launch_rollout_fwd_impl(const SimArgs &a, const float2 *actions, int T, int C,

@@ -317,7 +317,8 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             const float L = in.L;
             if (mode == kModeStep && (f & GD_FLAG_ALIVE)) {
                 if (!(isfinite(in.act.x) && isfinite(in.act.y))) nonfinite = true;
-                bicycle(x, y, yaw, v, L, in.act.x, in.act.y, a.dt, a.vmax);
+                if (a.dyn == GD_DYN_DELTA) delta_model(x, y, yaw, v, in.act.x, in.act.y, a.dt);
+                else bicycle(x, y, yaw, v, L, in.act.x, in.act.y, a.dt, a.vmax);
                 a.x[gi] = x;
                 a.y[gi] = y;
                 a.yaw[gi] = yaw;

@@ -20,11 +20,13 @@ GD_FLAG_COLL_AGENT, GD_FLAG_COLL_EDGE, GD_FLAG_GOAL, GD_FLAG_DONE, GD_FLAG_ALIVE
 GD_AUTO_RESET, GD_TERMINATE_ON_COLLISION, GD_CHECK_FINITE, GD_USE_GRAPH = 1, 2, 4, 8
 
 ENTRY_POINTS = ("gd_partner_slots", "gd_workspace_size", "gd_create", "gd_reset", "gd_step",
-                "gd_obs", "gd_rollout_fwd", "gd_rollout_bwd", "gd_set_obs_buffers", "gd_set_timing",
+                "gd_obs", "gd_rollout_fwd", "gd_rollout_bwd", "gd_invert_actions",
+                "gd_set_obs_buffers", "gd_set_timing",
                 "gd_get_timing", "gd_check", "gd_destroy", "gd_last_error")
 GD_ROAD_AUTO, GD_ROAD_LDS, GD_ROAD_GLOBAL = 0, 1, 2
-GD_PHASE_STEP, GD_PHASE_LIDAR, GD_PHASE_ROLLOUT_FWD, GD_PHASE_ROLLOUT_BWD = range(4)
-GD_NUM_PHASES = 4
+GD_DYN_BICYCLE, GD_DYN_DELTA = 0, 1
+GD_PHASE_STEP, GD_PHASE_LIDAR, GD_PHASE_ROLLOUT_FWD, GD_PHASE_ROLLOUT_BWD, GD_PHASE_INVERT = range(5)
+GD_NUM_PHASES = 5
 
 
 class GDError(RuntimeError):
@@ -39,7 +41,7 @@ class gd_config(C.Structure):
                 ("dt", C.c_float), ("obs_radius", C.c_float), ("goal_radius", C.c_float),
                 ("v_max", C.c_float), ("lidar_range", C.c_float), ("collision_penalty", C.c_float),
                 ("cell_size", C.c_float), ("obs_waves", C.c_int32), ("obs_bins", C.c_int32),
-                ("obs_cands", C.c_int32), ("obs_road", C.c_int32), ("reserved", C.c_int32)]
+                ("obs_cands", C.c_int32), ("obs_road", C.c_int32), ("dynamics", C.c_int32)]
 
 
 _BUF_FIELDS = ("agent_off", "road_off", "x", "y", "yaw", "speed", "length", "width", "goal_x",
@@ -74,6 +76,7 @@ def lib():
             "gd_obs": [vp, vp],
             "gd_rollout_fwd": [vp, vp, i32, i32, vp, vp, vp],
             "gd_rollout_bwd": [vp, vp, vp, i32, i32, vp, vp, vp, vp],
+            "gd_invert_actions": [vp, vp, i32, vp, vp],
             "gd_set_obs_buffers": [vp, C.POINTER(gd_buffers)],
             "gd_set_timing": [vp, i32],
             "gd_get_timing": [vp, vp, vp],
@@ -144,6 +147,11 @@ def gd_rollout_bwd(sim, actions_ptr: int, ckpt_ptr: int, T: int, ckpt_every: int
     _check(lib().gd_rollout_bwd(sim, C.c_void_p(actions_ptr), C.c_void_p(ckpt_ptr), T, ckpt_every,
                                 C.c_void_p(grad_rewards_ptr), C.c_void_p(grad_actions_ptr),
                                 C.c_void_p(grad_state0_ptr or 0), C.c_void_p(stream)))
+
+
+def gd_invert_actions(sim, states_ptr: int, T: int, actions_ptr: int, stream: int):
+    _check(lib().gd_invert_actions(sim, C.c_void_p(states_ptr), T, C.c_void_p(actions_ptr),
+                                   C.c_void_p(stream)))
 
 
 def gd_set_obs_buffers(sim, bufs: gd_buffers):

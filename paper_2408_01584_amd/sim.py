@@ -38,6 +38,7 @@ def config_from_params(p, num_worlds: int, graph: bool = False, check_finite: bo
     c.obs_bins = obs_bins
     c.obs_cands = obs_cands
     c.obs_road = obs_road
+    c.dynamics = getattr(p, "dynamics", G.GD_DYN_BICYCLE)
     return c
 
 
@@ -185,6 +186,17 @@ class Sim:
                          grad_rewards.contiguous().data_ptr(), ga.data_ptr(),
                          None if g0 is None else g0.data_ptr(), _stream())
         return ga, g0
+
+
+    # ---- expert-action inversion (simplified model)
+    def invert_actions(self, states: torch.Tensor) -> torch.Tensor:
+        """states [T+1, 4, A] (x, y, yaw, speed) -> actions [T, A, 2] that replay them."""
+        assert states.dtype == torch.float32 and states.is_contiguous()
+        assert states.dim() == 3 and states.shape[1] == 4 and states.shape[2] == self.A
+        T = states.shape[0] - 1
+        actions = torch.empty((max(T, 0), self.A, 2), dtype=torch.float32, device=self.device)
+        G.gd_invert_actions(self.handle, states.data_ptr(), T, actions.data_ptr(), _stream())
+        return actions
 
 
 class DiffRollout(torch.autograd.Function):

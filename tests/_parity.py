@@ -63,13 +63,14 @@ def oracle_for(scene, state, flags, t, O, params=None):
 
 def teacher_forced_run(scene, sim, O, actions, steps, stats=None):
     """Step the GPU `steps` times; before each step hand its state to the oracle, step the
-    oracle in FP64 and compare; then compare the observation of the GPU's new state."""
+    oracle in FP64 (with the GPU simulator's parameters) and compare; then compare the
+    observation of the GPU's new state."""
     K, N = scene.params.top_k, scene.params.lidar_rays
     stats = stats if stats is not None else {}
     stats.setdefault("band_worlds", 0)
     stats.setdefault("max_state_rel", 0.0)
     g = sim.host_outputs()
-    orc = oracle_for(scene, g["state"], g["flags"], g["t"], O)
+    orc = oracle_for(scene, g["state"], g["flags"], g["t"], O, sim.params)
     compare_obs(g, orc.obs(), K, N)
     import torch
     for k in range(steps):
@@ -77,7 +78,7 @@ def teacher_forced_run(scene, sim, O, actions, steps, stats=None):
         act = torch.as_tensor(np.ascontiguousarray(actions[k]), device=sim.device)
         sim.step(act)
         g = sim.host_outputs()
-        orc = oracle_for(scene, pre["state"], pre["flags"], pre["t"], O)
+        orc = oracle_for(scene, pre["state"], pre["flags"], pre["t"], O, sim.params)
         o = orc.step(actions[k].astype(np.float64))
         # worlds whose discrete outcome sits within 1e-4 m of a threshold are not compared
         skip_w = np.zeros(scene.num_worlds, bool)
@@ -98,6 +99,6 @@ def teacher_forced_run(scene, sim, O, actions, steps, stats=None):
         rel = np.abs(st_g - st_o) / np.maximum(np.abs(st_o), 1.0)
         stats["max_state_rel"] = max(stats["max_state_rel"], float(rel.max()) if rel.size else 0.0)
         # observation of the GPU's new state, teacher-forced
-        orc2 = oracle_for(scene, g["state"], g["flags"], g["t"], O)
+        orc2 = oracle_for(scene, g["state"], g["flags"], g["t"], O, sim.params)
         compare_obs(g, orc2.obs(), K, N)
     return stats
