@@ -360,12 +360,23 @@ def delta_model_legs(scene, T, c):
     ms_inv = _timed(invert) / reps
     nbytes = A * ((T + 1) * 8 + T * 8)
     gbs = nbytes / (ms_inv * 1e-3) / 1e9
+    # a device-to-device copy moving the same bytes (half read, half written), for context
+    src = torch.empty(nbytes // 8, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+
+    def copy():
+        for _ in range(reps):
+            dst.copy_(src)
+    copy()
+    ms_copy = _timed(copy) / reps
+    del src, dst
     sim.close()
     return {"step_ms": round(ms / T, 5), "step_agent_steps_per_s": round(A * T / (ms / 1e3), 1),
             "invert": {"T": T, "ms_per_launch": round(ms_inv, 5),
                        "agent_steps_per_s": round(A * T / (ms_inv / 1e3), 1),
                        "algorithmic_bytes_per_launch": nbytes, "achieved_GBps": round(gbs, 1),
-                       "hbm_frac": round(gbs * 1e9 / HBM_PEAK, 4)}}
+                       "hbm_frac": round(gbs * 1e9 / HBM_PEAK, 4),
+                       "same_bytes_copy_GBps": round(nbytes / (ms_copy * 1e-3) / 1e9, 1)}}
 
 
 def cpu_baseline(cfg_id, steps):

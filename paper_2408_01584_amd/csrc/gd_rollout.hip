@@ -375,9 +375,20 @@ __device__ __forceinline__ float wrap_diff(float y1, float y0) {
     return r;
 }
 
-// Expert-action inversion of the simplified model: one thread per agent and chunk of
-// kInvChunk steps, all of the chunk's (yaw, speed) rows loaded before any action is
-// formed.  Row t0 + kInvChunk is read by two chunks.
+// Actions of one step of the simplified model from the heading and speed before (0) and
+// after (1) it.
+__device__ __forceinline__ float2 invert_step(float y0, float y1, float v0, float v1, float dt) {
+    const float acc = (v1 - v0) / dt;
+    const float d = 0.5f * (v0 + v1) * dt;
+    const float w = wrap_diff(y1, y0);
+    return make_float2(acc, fabsf(d) < 1e-3f ? 0.0f : w / d);
+}
+
+// Expert-action inversion of the simplified model, HBM-bound (reads heading and speed of
+// each state once per chunk, writes each action once): one thread per agent and chunk
+// of kInvChunk steps, all of the chunk's rows loaded before any action is formed.  Row
+// t0 + kInvChunk is read by two chunks.  (Four agents per thread with 16-byte accesses
+// measured slower.)
 constexpr int kInvThreads = 256;
 constexpr int kInvChunk = 16;
 
@@ -402,13 +413,7 @@ __global__ __launch_bounds__(kInvThreads) void k_invert_actions(const float *__r
 #pragma unroll
     for (int k = 0; k < kInvChunk; k++) {
         const int t = t0 + k;
-        if (t < T) {
-            const float acc = (vv[k + 1] - vv[k]) / dt;
-            const float d = 0.5f * (vv[k] + vv[k + 1]) * dt;
-            const float w = wrap_diff(yw[k + 1], yw[k]);
-            const float s = fabsf(d) < 1e-3f ? 0.0f : w / d;
-            act[(size_t)t * As + i] = make_float2(acc, s);
-        }
+        if (t < T) act[(size_t)t * As + i] = invert_step(yw[k], yw[k + 1], vv[k], vv[k + 1], dt);
     }
 }
 
