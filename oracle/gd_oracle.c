@@ -18,7 +18,8 @@
  *                                                 (Sec. 3.2 "Rewards", "Termination")
  *   - radius-filter observations in the agent's relative frame: partner states and the
  *     nearest road points within the radius                (Fig. 1; Sec. 3.2 "Sensor modalities")
- *   - planar LIDAR against road edges and agent boxes     (Sec. 3.2 "Sensor modalities")
+ *   - planar LIDAR against road edges and agent boxes, as a full ring or as a view cone
+ *     turned by a head-rotation input                   (Sec. 3.2 "Sensor modalities")
  *   - a smooth goal/off-road reward and its hand-derived vector-Jacobian product for
  *     differentiable rollouts (an extension; the reward shape follows the configurable
  *     "agent-road distance" rewards of Sec. 3.2 "Rewards").
@@ -62,6 +63,7 @@ typedef struct {
     uint32_t flags;
     double dt, obs_radius, goal_radius, v_max, lidar_range, collision_penalty;
     int32_t model; /* OR_MODEL_BICYCLE or OR_MODEL_DELTA */
+    double lidar_fov; /* 0: rays around the full circle; (0, 2 pi]: view cone of this width */
 } or_config;
 
 #define OR_MODEL_BICYCLE 0
@@ -81,6 +83,8 @@ typedef struct {
     const int32_t *rmeta;
     uint8_t *flags;                                /* [A] */
     int32_t *t;                                    /* [W] */
+    const double *head;                            /* [A] head angle of the view cone
+                                                      (rad, from the heading); NULL = 0 */
 } or_batch;
 
 typedef struct {
@@ -444,10 +448,16 @@ static void obs_world(const or_batch *b, const or_config *c, int w, const or_out
             double dN = hypot(b->rx[kn] - px, b->ry[kn] - py);
             if (fabs(dN - dK) < OR_BAND) o->band[i] |= 8;
         }
-        /* LIDAR: N rays from the box centre, evenly spaced from the heading; nearest hit
-           on a road-edge segment (type 1) or another visible agent's box side (type 2) */
+        /* LIDAR: N rays from the box centre, evenly spaced around the circle from the
+           heading, or, for a view cone of width fov, spread evenly over the cone centred
+           on the heading turned by the agent's head angle (ray k at the centre of the
+           k-th of N equal sub-arcs); nearest hit on a road-edge segment (type 1) or
+           another visible agent's box side (type 2) */
+        int cone = c->lidar_fov > 0.0;
+        double head = b->head ? b->head[i] : 0.0;
         for (int k = 0; k < N; k++) {
-            double ang = th + 2.0 * OR_PI * (double)k / (double)N;
+            double ang = cone ? th + head + c->lidar_fov * (((double)k + 0.5) / (double)N - 0.5)
+                              : th + 2.0 * OR_PI * (double)k / (double)N;
             double dx = cos(ang), dy = sin(ang);
             double best = c->lidar_range, second = INFINITY;
             int hit = 0;

@@ -52,14 +52,14 @@ class Config(C.Structure):
                 ("lidar_rays", C.c_int32), ("flags", C.c_uint32), ("dt", C.c_double),
                 ("obs_radius", C.c_double), ("goal_radius", C.c_double), ("v_max", C.c_double),
                 ("lidar_range", C.c_double), ("collision_penalty", C.c_double),
-                ("model", C.c_int32)]
+                ("model", C.c_int32), ("lidar_fov", C.c_double)]
 
 
 class Batch(C.Structure):
     _fields_ = [("W", C.c_int32), ("agent_off", C.c_void_p), ("road_off", C.c_void_p)] + \
         [(n, C.c_void_p) for n in ("x", "y", "yaw", "v", "len", "wid", "gx", "gy", "snap_x",
                                    "snap_y", "snap_yaw", "snap_v", "rx", "ry", "rdir", "rmeta",
-                                   "flags", "t")]
+                                   "flags", "t", "head")]
 
 
 class Outputs(C.Structure):
@@ -94,7 +94,7 @@ def config_from_params(p) -> Config:
     flags = (AUTO_RESET if p.auto_reset else 0) | (TERM_ON_COLLISION if p.terminate_on_collision else 0)
     return Config(p.top_k, p.partners, p.episode_len, p.lidar_rays, flags, p.dt, p.obs_radius,
                   p.goal_radius, p.v_max, p.lidar_range, p.collision_penalty,
-                  getattr(p, "dynamics", MODEL_BICYCLE))
+                  getattr(p, "dynamics", MODEL_BICYCLE), getattr(p, "lidar_fov", 0.0))
 
 
 def partner_slots(agent_off: np.ndarray, partners: int) -> int:
@@ -171,6 +171,7 @@ class OracleSim:
         self.W = len(self.agent_off) - 1
         self.A = int(self.agent_off[-1])
         self.flags = np.full(self.A, ALIVE | VISIBLE, dtype=np.uint8)
+        self.head = np.zeros(self.A)  # view-cone head angles (rad, from the heading)
         self.t = np.zeros(self.W, dtype=np.int32)
         p = self.params
         self.K, self.N = p.top_k, p.lidar_rays
@@ -194,6 +195,7 @@ class OracleSim:
         b.snap_x, b.snap_y, b.snap_yaw, b.snap_v = (_p(a) for a in self.snap)
         b.rx, b.ry, b.rdir, b.rmeta = _p(self.rx), _p(self.ry), _p(self.rdir), _p(self.rmeta)
         b.flags, b.t = _p(self.flags), _p(self.t)
+        b.head = _p(self.head)
         self._keep = b
         return b
 
@@ -216,8 +218,8 @@ class OracleSim:
         return r
 
     # -- state access (teacher forcing) --
-    def set_state(self, x=None, y=None, yaw=None, v=None, flags=None, t=None):
-        for name, val in (("x", x), ("y", y), ("yaw", yaw), ("v", v)):
+    def set_state(self, x=None, y=None, yaw=None, v=None, flags=None, t=None, head=None):
+        for name, val in (("x", x), ("y", y), ("yaw", yaw), ("v", v), ("head", head)):
             if val is not None:
                 getattr(self, name)[:] = np.asarray(val, dtype=np.float64)
         if flags is not None:

@@ -65,6 +65,7 @@ class SimParams:
     auto_reset: bool = True
     terminate_on_collision: bool = False
     dynamics: int = 0  # 0: bicycle model (App. B); 1: simplified model (Sec. 3.2 "Dynamics")
+    lidar_fov: float = 0.0  # 0: LIDAR rays around the full circle; > 0: view-cone width (rad)
 
 
 @dataclass(frozen=True)
