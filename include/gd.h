@@ -124,6 +124,10 @@ typedef struct {
                                   (from the workspace through the caches) or GD_ROAD_AUTO
                                   (staged when that keeps as many resident waves) */
     int32_t dynamics;          /* GD_DYN_BICYCLE or GD_DYN_DELTA */
+    float lidar_fov;           /* 0: LIDAR rays around the full circle; in [1e-4, 2 pi]:
+                                  a view cone of this width (rad) turned by the per-agent
+                                  head angle gd_buffers.lidar_head (Sec. 3.2 "Sensor
+                                  modalities") */
 } gd_config;
 
 typedef struct {
@@ -148,6 +152,9 @@ typedef struct {
     uint8_t *flags;            /* [A] GD_FLAG_* */
     uint8_t *world_done;       /* [W] 1 = the world finished in the last step */
     int32_t *t;                /* [W] step counter of the current episode */
+    const float *lidar_head;   /* [A] head angle of the view cone from the heading (rad),
+                                  written by the caller before each step (the head-rotation
+                                  action); read only when lidar_fov > 0; NULL = 0 */
     void *workspace;           /* device scratch of at least workspace_bytes */
     size_t workspace_bytes;
 } gd_buffers;
@@ -207,9 +214,10 @@ gd_status gd_step(gd_sim *sim, const float *actions, void *stream);
  *            distance, world-local index) in ascending order, each as (x', y',
  *            wrap(dir - yaw_i), type); radius test and ranking key are binary32,
  *            dx = q_x - p_x, dy = q_y - p_y, d2 = dx*dx + dy*dy, rounded per operation;
- *   lidar  : N rays from the box centre at yaw_i + 2 pi k / N; nearest hit in (0, range]
- *            on a road-edge segment (1) or another VISIBLE agent's box (2), else range
- *            and 0. */
+ *   lidar  : N rays from the box centre at yaw_i + 2 pi k / N, or, with a view cone
+ *            (lidar_fov > 0), at yaw_i + head_i + fov ((k + 1/2) / N - 1/2); nearest hit
+ *            in (0, range] on a road-edge segment (1) or another VISIBLE agent's box (2),
+ *            else range and 0. */
 gd_status gd_obs(gd_sim *sim, void *stream);
 
 /* Differentiable rollout (forward).  Starting from the current state (the state buffers

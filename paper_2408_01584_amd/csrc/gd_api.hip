@@ -140,6 +140,8 @@ static gd_status check_config(const gd_config *c, const int32_t *h_agent_off,
         return fail(GD_E_ARG, "obs_cands must be 0, 128, 256, 384, 512, 768 or 1024");
     if (!(c->obs_road == GD_ROAD_AUTO || c->obs_road == GD_ROAD_LDS || c->obs_road == GD_ROAD_GLOBAL))
         return fail(GD_E_ARG, "obs_road must be GD_ROAD_AUTO, GD_ROAD_LDS or GD_ROAD_GLOBAL");
+    if (!(c->lidar_fov == 0.0f || (c->lidar_fov >= 1e-4f && c->lidar_fov <= 6.2831855f)))
+        return fail(GD_E_ARG, "lidar_fov must be 0 or in [1e-4, 2 pi]");
     if (!(c->dynamics == GD_DYN_BICYCLE || c->dynamics == GD_DYN_DELTA))
         return fail(GD_E_ARG, "dynamics must be GD_DYN_BICYCLE or GD_DYN_DELTA");
     const int W = c->num_worlds;
@@ -432,6 +434,7 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
     }
     a.vmax = cfg->v_max;
     a.lidar_range = cfg->lidar_range;
+    a.lidar_fov = cfg->lidar_fov;
     a.penalty = cfg->collision_penalty;
     a.agent_off = b->agent_off;
     a.road_off = b->road_off;
@@ -454,6 +457,7 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
     a.road_idx = b->road_idx;
     a.lidar = b->lidar;
     a.lidar_hit = b->lidar_hit;
+    a.head = b->lidar_head;
     a.reward = b->reward;
     a.fl = b->flags;
     a.world_done = b->world_done;

@@ -32,6 +32,7 @@ struct SimArgs {
     uint32_t flags;
     int dyn;  // GD_DYN_BICYCLE or GD_DYN_DELTA
     float dt, R_obs, R2_obs, goal_r2, vmax, lidar_range, penalty;
+    float lidar_fov;  // 0: full ring; > 0: view-cone width (rad)
 
     // caller buffers
     const int *agent_off, *road_off;
@@ -45,6 +46,7 @@ struct SimArgs {
     int *road_idx;
     float *lidar;
     int *lidar_hit;
+    const float *head;  // [A] view-cone head angles, NULL = 0
     float *reward;
     uint8_t *fl;
     uint8_t *world_done;

@@ -1,9 +1,12 @@
 // Planar LIDAR observation (Sec. 3.2 "Sensor modalities": rays cast from the agent, all
 // objects being boxes of fixed height, so the scan is two-dimensional).
 //
-// N rays leave the box centre of every visible agent at yaw + 2 pi k / N.  A ray reports
-// the nearest hit in (0, range] on a road-edge segment (type 1) or on a side of another
-// visible agent's box (type 2), else (range, 0).
+// N rays leave the box centre of every visible agent at yaw + 2 pi k / N, or, for a view
+// cone of width fov, at yaw + head + fov ((k + 1/2) / N - 1/2), the head angle being the
+// agent's head-rotation input.  A ray reports the nearest hit in (0, range] on a
+// road-edge segment (type 1) or on a side of another visible agent's box (type 2), else
+// (range, 0).  Everything below works in the frame of the ray fan (the heading, turned by
+// the head angle for a cone), in which the ray directions are the same for all agents.
 //
 // One workgroup per world.  The world's agents (position, heading, half extents, flags)
 // and, when they fit, its edge segments with their grid rows are staged in LDS first, so
@@ -35,11 +38,28 @@ __device__ __forceinline__ float ray_angle(float y, float x) {
     return y < 0.0f ? -r : r;
 }
 
+// Rays of the fan whose angle lies in [a0, a1] widened by 1 mrad on each side (far above
+// the angle error; widening only adds rays that the exact test then rejects).  Ring: ray k
+// at k / inv_step, indices taken modulo N.  Cone: ray k at (k + 1/2) / inv_step - half,
+// indices clamped to [0, N).
+template <bool CONE>
+__device__ __forceinline__ void fan_rays(float a0, float a1, int N, float inv_step, float half, int &k0,
+                                         int &k1) {
+    if (!CONE) {
+        k0 = (int)ceilf((a0 - 1e-3f) * inv_step);
+        k1 = (int)floorf((a1 + 1e-3f) * inv_step);
+        return;
+    }
+    k0 = (int)fmaxf(ceilf((a0 - 1e-3f + half) * inv_step - 0.5f), 0.0f);
+    k1 = (int)fminf(floorf((a1 + 1e-3f + half) * inv_step - 0.5f), (float)(N - 1));
+}
+
+template <bool CONE>
 __device__ __forceinline__ void lidar_candidate(float ax, float ay, float bx, float by,
-                                                unsigned type, int N, float inv_step,
+                                                unsigned type, int N, float inv_step, float half,
                                                 float range, const float2 *dirs,
                                                 unsigned long long *best) {
-    // a, b: segment endpoints in the ego frame (agent at the origin, heading +x)
+    // a, b: segment endpoints in the frame of the ray fan (agent at the origin)
     const float pa = ray_angle(ay, ax), pb = ray_angle(by, bx);
     float lo = pa, span = pb - pa;
     const float two_pi = 6.283185307179586f;
@@ -49,21 +69,32 @@ __device__ __forceinline__ void lidar_candidate(float ax, float ay, float bx, fl
         lo = pb;
         span = -span;
     }
-    // rays k with angle 2 pi k / N inside [lo, lo + span] widened by 1 mrad on each side
-    // (far above the angle error, below any ray spacing); an arc within 0.01 rad of pi
-    // (the segment passes next to the origin, where the rounded angles could pick the
-    // complementary arc) takes every ray
-    int k0 = (int)ceilf((lo - 1e-3f) * inv_step);
-    int k1 = (int)floorf((lo + span + 1e-3f) * inv_step);
-    if (k1 - k0 >= N - 1 || span > 3.13159265f) {
+    // the rays inside the arc [lo, lo + span]; an arc within 0.01 rad of pi (the segment
+    // passes next to the origin, where the rounded angles could pick the complementary
+    // arc) takes every ray.  A cone's rays lie in (-pi, pi), so the part of a (widened)
+    // arc beyond +-pi is looked up again one turn lower or higher.
+    int k0, k1, k2 = 0, k3 = -1;
+    fan_rays<CONE>(lo, lo + span, N, inv_step, half, k0, k1);
+    if (span > 3.13159265f || (!CONE && k1 - k0 >= N - 1)) {
         k0 = 0;
         k1 = N - 1;
+    } else if (CONE && lo + span + 1e-3f > 3.14159265f) {
+        fan_rays<CONE>(lo - two_pi, lo + span - two_pi, N, inv_step, half, k2, k3);
+    } else if (CONE && lo - 1e-3f < -3.14159265f) {
+        fan_rays<CONE>(lo + two_pi, lo + span + two_pi, N, inv_step, half, k2, k3);
     }
     const float ex = bx - ax, ey = by - ay;
     const float nt = ax * ey - ay * ex;  // t = nt / den along the ray
-    for (int kk = k0; kk <= k1; kk++) {
-        int k = kk % N;
-        if (k < 0) k += N;
+    const int n01 = k1 >= k0 ? k1 - k0 + 1 : 0;
+    const int nall = CONE ? n01 + (k3 >= k2 ? k3 - k2 + 1 : 0) : n01;
+    for (int m = 0; m < nall; m++) {
+        int k;
+        if (CONE) {
+            k = m < n01 ? k0 + m : k2 + (m - n01);  // in [0, N) already
+        } else {
+            k = (k0 + m) % N;
+            if (k < 0) k += N;
+        }
         const float2 d = dirs[k];
         // ray t*d against a + s*e: t = nt / den, s = ns / den; the range tests are taken
         // on the numerators (signs and magnitudes), the division only for a hit
@@ -120,6 +151,7 @@ __host__ __device__ inline LidarLds lidar_layout(int N, int waves, int agent_cap
     return L;
 }
 
+template <bool CONE>
 __global__ __launch_bounds__(kLidarMaxWaves * kWave) void k_lidar(SimArgs a, LidarCtl lc) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = a.N;
@@ -148,12 +180,17 @@ __global__ __launch_bounds__(kLidarMaxWaves * kWave) void k_lidar(SimArgs a, Lid
     const int ncell = g.nx * g.ny;
     const bool staged = lc.edge_cap > 0;
     const float range = a.lidar_range;
-    const float inv_step = (float)N / 6.283185307179586f;
+    const float fov = CONE ? a.lidar_fov : 6.283185307179586f;
+    const float inv_step = (float)N / fov;
+    const float half = 0.5f * fov;
 
-    // staging: ray directions, the world's agents, its edge segments and their grid rows
+    // staging: ray directions in the frame of the fan, the world's agents, its edge
+    // segments and their grid rows
     for (int k = threadIdx.x; k < N; k += blockDim.x) {
         float s, c;
-        sincosf(6.283185307179586f * (float)k / (float)N, &s, &c);
+        const float ang = CONE ? fov * (((float)k + 0.5f) / (float)N - 0.5f)
+                               : 6.283185307179586f * (float)k / (float)N;
+        sincosf(ang, &s, &c);
         dirs[k] = make_float2(c, s);
     }
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -193,7 +230,15 @@ __global__ __launch_bounds__(kLidarMaxWaves * kWave) void k_lidar(SimArgs a, Lid
             continue;
         }
         const float px = lidar_uniform(sx[l]), py = lidar_uniform(sy[l]);
-        const float cs = lidar_uniform(sc[l]), sn = lidar_uniform(ss[l]);
+        float cs = lidar_uniform(sc[l]), sn = lidar_uniform(ss[l]);
+        if (CONE && a.head) {
+            // frame of the fan: the heading turned by the head angle
+            float sh, ch;
+            sincosf(a.head[ai], &sh, &ch);
+            const float c2 = cs * ch - sn * sh, s2 = sn * ch + cs * sh;
+            cs = lidar_uniform(c2);
+            sn = lidar_uniform(s2);
+        }
         const unsigned long long none = ((unsigned long long)__float_as_uint(range) << 32) | 0u;
         for (int k = lane; k < N; k += kWave) best[k] = ~0ull;
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -208,7 +253,7 @@ __global__ __launch_bounds__(kLidarMaxWaves * kWave) void k_lidar(SimArgs a, Lid
             __builtin_amdgcn_wave_barrier();
             for (int e = lane; e < nl; e += kWave) {
                 const float4 v = lst[e];
-                lidar_candidate(v.x, v.y, v.z, v.w, ltype[e], N, inv_step, range, dirs, best);
+                lidar_candidate<CONE>(v.x, v.y, v.z, v.w, ltype[e], N, inv_step, half, range, dirs, best);
             }
             nl = 0;
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -317,12 +362,17 @@ size_t lidar_lds_bytes(int N, const LidarCtl &lc) {
     return lidar_layout(N, lc.waves, lc.agent_cap, lc.edge_cap, lc.cell_cap4).total;
 }
 
-static hipError_t lidar_prepare(size_t lds) {
-    static size_t allowed = 0;
-    if (lds > allowed) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_lidar, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+static const void *lidar_kernel(const SimArgs &a) {
+    return a.lidar_fov > 0.0f ? (const void *)k_lidar<true> : (const void *)k_lidar<false>;
+}
+
+static hipError_t lidar_prepare(const SimArgs &a, size_t lds) {
+    static size_t allowed[2] = {0, 0};
+    size_t &al = allowed[a.lidar_fov > 0.0f ? 1 : 0];
+    if (lds > al) {
+        hipError_t e = hipFuncSetAttribute(lidar_kernel(a), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        allowed = lds;
+        al = lds;
     }
     return hipSuccess;
 }
@@ -330,16 +380,17 @@ static hipError_t lidar_prepare(size_t lds) {
 hipError_t launch_lidar_impl(const SimArgs &a, const LidarCtl &lc, hipStream_t s) {
     if (a.N <= 0 || a.W <= 0) return hipSuccess;
     const size_t lds = lidar_lds_bytes(a.N, lc);
-    hipError_t e = lidar_prepare(lds);
+    hipError_t e = lidar_prepare(a, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_lidar, dim3(a.W), dim3(lc.waves * kWave), lds, s, a, lc);
+    if (a.lidar_fov > 0.0f) hipLaunchKernelGGL(k_lidar<true>, dim3(a.W), dim3(lc.waves * kWave), lds, s, a, lc);
+    else hipLaunchKernelGGL(k_lidar<false>, dim3(a.W), dim3(lc.waves * kWave), lds, s, a, lc);
     return hipGetLastError();
 }
 
 bool lidar_kernel_node(const SimArgs *a, const LidarCtl *lc, hipKernelNodeParams &p, void **args) {
     const size_t lds = lidar_lds_bytes(a->N, *lc);
-    if (lidar_prepare(lds) != hipSuccess) return false;
-    p.func = (void *)k_lidar;
+    if (lidar_prepare(*a, lds) != hipSuccess) return false;
+    p.func = const_cast<void *>(lidar_kernel(*a));
     p.gridDim = dim3(a->W);
     p.blockDim = dim3(lc->waves * kWave);
     p.sharedMemBytes = (unsigned)lds;

@@ -34,19 +34,25 @@
 
 namespace gdk {
 
-// ---- bicycle model (App. B): midpoint speed, slip angle with l_r = L/2, explicit Euler
-__device__ __forceinline__ void bicycle(float &x, float &y, float &yaw, float &v, float L,
-                                        float acc, float steer, float dt, float vmax) {
-    float vb = fminf(fmaxf(v + 0.5f * acc * dt, -vmax), vmax);
-    float ts = tanf(steer);
-    float beta = atanf(0.5f * ts);
+// ---- dynamics.  Bicycle model (App. B): midpoint speed clipped to +-v_max, slip angle
+// beta = atan(tan(steer)/2) (l_r = L/2), explicit Euler.  The simplified model (Sec. 3.2
+// "Dynamics") is the same update with beta = 0, the command u as the curvature and no
+// clip: with vb = v + a dt/2 the distance of the step is vb dt = v dt + a dt^2/2.  Both
+// go through one code path with selects, so that the step kernel carries one copy of it.
+__device__ __forceinline__ void move_agent(float &x, float &y, float &yaw, float &v, float L,
+                                           float acc, float u, float dt, float vmax, bool delta) {
+    const float lim = delta ? INFINITY : vmax;
+    const float vb = fminf(fmaxf(v + 0.5f * acc * dt, -lim), lim);
+    const float ts = tanf(u);
+    const float beta = delta ? 0.0f : atanf(0.5f * ts);
     float sp, cp;
     sincosf(yaw + beta, &sp, &cp);
-    float cb = cosf(beta);
+    const float cb = cosf(beta);
+    const float turn = delta ? vb * u * dt : vb * cb * ts / L * dt;
     x = x + vb * cp * dt;
     y = y + vb * sp * dt;
-    yaw = yaw + vb * cb * ts / L * dt;
-    v = fminf(fmaxf(v + acc * dt, -vmax), vmax);
+    yaw = yaw + turn;
+    v = fminf(fmaxf(v + acc * dt, -lim), lim);
 }
 
 // ---- separating-axis tests in FP32, coordinates relative to box i's centre
@@ -317,8 +323,7 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             const float L = in.L;
             if (mode == kModeStep && (f & GD_FLAG_ALIVE)) {
                 if (!(isfinite(in.act.x) && isfinite(in.act.y))) nonfinite = true;
-                if (a.dyn == GD_DYN_DELTA) delta_model(x, y, yaw, v, in.act.x, in.act.y, a.dt);
-                else bicycle(x, y, yaw, v, L, in.act.x, in.act.y, a.dt, a.vmax);
+                move_agent(x, y, yaw, v, L, in.act.x, in.act.y, a.dt, a.vmax, a.dyn == GD_DYN_DELTA);
                 a.x[gi] = x;
                 a.y[gi] = y;
                 a.yaw[gi] = yaw;

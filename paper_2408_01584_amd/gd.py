@@ -41,13 +41,14 @@ class gd_config(C.Structure):
                 ("dt", C.c_float), ("obs_radius", C.c_float), ("goal_radius", C.c_float),
                 ("v_max", C.c_float), ("lidar_range", C.c_float), ("collision_penalty", C.c_float),
                 ("cell_size", C.c_float), ("obs_waves", C.c_int32), ("obs_bins", C.c_int32),
-                ("obs_cands", C.c_int32), ("obs_road", C.c_int32), ("dynamics", C.c_int32)]
+                ("obs_cands", C.c_int32), ("obs_road", C.c_int32), ("dynamics", C.c_int32),
+                ("lidar_fov", C.c_float)]
 
 
 _BUF_FIELDS = ("agent_off", "road_off", "x", "y", "yaw", "speed", "length", "width", "goal_x",
                "goal_y", "road_x", "road_y", "road_dir", "road_meta", "obs_ego", "obs_partner",
                "partner_mask", "obs_road", "road_idx", "lidar", "lidar_hit", "reward", "flags",
-               "world_done", "t", "workspace")
+               "world_done", "t", "lidar_head", "workspace")
 
 
 class gd_buffers(C.Structure):

@@ -39,6 +39,7 @@ def config_from_params(p, num_worlds: int, graph: bool = False, check_finite: bo
     c.obs_cands = obs_cands
     c.obs_road = obs_road
     c.dynamics = getattr(p, "dynamics", G.GD_DYN_BICYCLE)
+    c.lidar_fov = getattr(p, "lidar_fov", 0.0)
     return c
 
 
@@ -88,6 +89,7 @@ class Sim:
         b["flags"] = torch.zeros(A, dtype=torch.uint8, device=dev)
         b["world_done"] = torch.zeros(W, dtype=torch.uint8, device=dev)
         b["t"] = torch.zeros(W, dtype=torch.int32, device=dev)
+        b["lidar_head"] = torch.zeros(max(A, 1), dtype=torch.float32, device=dev)  # head angles
         b["workspace"] = torch.empty(ws + 256, dtype=torch.uint8, device=dev)
         self.buf = b
         bufs = G.gd_buffers()
