@@ -20,6 +20,7 @@
  *     nearest road points within the radius                (Fig. 1; Sec. 3.2 "Sensor modalities")
  *   - planar LIDAR against road edges and agent boxes, as a full ring or as a view cone
  *     turned by a head-rotation input                   (Sec. 3.2 "Sensor modalities")
+ *   - Visvalingam-Whyatt decimation of the road polylines at ingest           (Sec. 3.1)
  *   - a smooth goal/off-road reward and its hand-derived vector-Jacobian product for
  *     differentiable rollouts (an extension; the reward shape follows the configurable
  *     "agent-road distance" rewards of Sec. 3.2 "Rewards").
@@ -912,5 +913,64 @@ void or_rollout_vjp(const or_batch *b, const or_config *c, int T, const double *
             free(S);
             free(SC);
         }
+    }
+}
+
+/* ------------------------------------------------------------------ polyline decimation (Sec. 3.1)
+
+   Visvalingam-Whyatt decimation of each polyline p_s .. p_{e-1} (CSR offsets poly_off):
+   the effective area of an interior point is the area of the triangle it forms with its
+   current neighbours; the interior point of smallest effective area (ties: lowest index)
+   is removed and its neighbours' areas recomputed, until every remaining interior point
+   has an area of at least min_area.  End points are always kept.  The areas decide which
+   points survive, so they are taken in binary32 with a fixed operation order,
+       A = |fl(fl(ux*vy) - fl(uy*vx))| / 2,  u = fl(b - a), v = fl(c - a),
+   a, b, c the previous, current and next point.  keep[p] = 1 for surviving points;
+   dir[p] (kept points) = angle of the vector to the next kept point of the polyline, the
+   last point repeating its predecessor's angle (FP64). */
+static float tri_area32(const float *x, const float *y, int a, int b, int c) {
+    volatile float ux = x[b] - x[a], uy = y[b] - y[a];
+    volatile float vx = x[c] - x[a], vy = y[c] - y[a];
+    volatile float p = ux * vy, q = uy * vx;
+    volatile float cr = p - q;
+    return 0.5f * fabsf(cr);
+}
+
+void or_decimate(int n_poly, const int32_t *poly_off, const float *x, const float *y,
+                 float min_area, uint8_t *keep, double *dir) {
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int pl = 0; pl < n_poly; pl++) {
+        int s = poly_off[pl], e = poly_off[pl + 1], n = e - s;
+        if (n <= 0) continue;
+        int *prv = (int *)malloc(sizeof(int) * (size_t)n);
+        int *nxt = (int *)malloc(sizeof(int) * (size_t)n);
+        for (int k = 0; k < n; k++) {
+            prv[k] = k - 1;
+            nxt[k] = k + 1;
+            keep[s + k] = 1;
+        }
+        for (;;) {
+            int best = -1;
+            float ba = 0.0f;
+            for (int k = nxt[0]; k < n - 1; k = nxt[k]) {
+                float a = tri_area32(x, y, s + prv[k], s + k, s + nxt[k]);
+                if (best < 0 || a < ba) {
+                    best = k;
+                    ba = a;
+                }
+            }
+            if (best < 0 || !(ba < min_area)) break;
+            keep[s + best] = 0;
+            nxt[prv[best]] = nxt[best];
+            prv[nxt[best]] = prv[best];
+        }
+        for (int k = 0; k < n; k = nxt[k]) {
+            int j = nxt[k] < n ? nxt[k] : -1;
+            if (j >= 0) dir[s + k] = atan2((double)y[s + j] - y[s + k], (double)x[s + j] - x[s + k]);
+            else if (prv[k] >= 0) dir[s + k] = atan2((double)y[s + k] - y[s + prv[k]], (double)x[s + k] - x[s + prv[k]]);
+            else dir[s + k] = 0.0;
+        }
+        free(prv);
+        free(nxt);
     }
 }

@@ -72,6 +72,7 @@ def _declare(L):
     L.or_dynamics.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, d, d]
     L.or_delta.argtypes = [i32, vp, vp, vp, vp, vp, vp, d]
     L.or_delta_invert.argtypes = [i32, i32, vp, d, vp, vp]
+    L.or_decimate.argtypes = [i32, vp, vp, vp, C.c_float, vp, vp]
     L.or_box_box_sep.argtypes = [vp, vp]
     L.or_box_box_sep.restype = d
     L.or_box_seg_sep.argtypes = [vp, d, d, d, d]
@@ -134,6 +135,18 @@ def invert_actions(states, dt=0.1):
     band = np.zeros((max(T, 0), n), np.uint8)
     lib().or_delta_invert(n, T, _p(st), dt, _p(act), _p(band))
     return act, band
+
+
+def decimate(poly_off, x, y, min_area):
+    """Visvalingam-Whyatt decimation (Sec. 3.1) of the polylines with CSR offsets
+    poly_off over binary32 points x, y: (keep [n] uint8, dir [n] float64 for kept points)."""
+    po = np.ascontiguousarray(poly_off, dtype=np.int32)
+    xs = np.ascontiguousarray(x, dtype=np.float32)
+    ys = np.ascontiguousarray(y, dtype=np.float32)
+    keep = np.zeros(len(xs), np.uint8)
+    dr = np.zeros(len(xs))
+    lib().or_decimate(len(po) - 1, _p(po), _p(xs), _p(ys), float(min_area), _p(keep), _p(dr))
+    return keep, dr
 
 
 def box_box_sep(a, b) -> float:
