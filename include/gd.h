@@ -15,6 +15,7 @@
  *                                            (Fig. 1; Sec. 3.2 "Sensor modalities")
  *   - goal reward, collision penalty, termination and removal (Sec. 3.2 "Rewards",
  *     "Termination")
+ *   - Visvalingam-Whyatt decimation of the road polylines at ingest          (Sec. 3.1)
  *
  * Conventions (all entry points):
  *   - Every array argument is a DEVICE pointer into caller-owned memory unless its name
@@ -259,6 +260,26 @@ gd_status gd_rollout_bwd(gd_sim *sim, const float *actions, const float *ckpt, i
  * actions must not overlap.  Asynchronous on `stream`. */
 gd_status gd_invert_actions(gd_sim *sim, const float *states, int32_t T, float *actions,
                             void *stream);
+
+/* Polyline decimation at ingest (Sec. 3.1: road polylines sampled every 0.1 m are thinned
+ * with the Visvalingam-Whyatt algorithm, cutting points, memory and step time).  The
+ * polylines are given by device CSR offsets poly_off [n_poly+1] into device points x, y
+ * [n_points] (binary32, m).  For each polyline the interior point whose triangle with its
+ * current neighbours has the smallest area (ties: lowest index) is removed, and its
+ * neighbours' areas recomputed, until every remaining interior point spans at least
+ * min_area (m^2); end points are always kept.  The area of (a, b, c) is
+ * |fl(fl(ux*vy) - fl(uy*vx))| / 2 with u = fl(b - a), v = fl(c - a) in binary32, rounded per
+ * operation.  Writes keep [n_points] (1 = kept) and dir [n_points] (kept points: angle of
+ * the vector to the next kept point of the polyline, the last point repeating its
+ * predecessor's; 0 for removed points).  Offsets outside [0, n_points] are clamped.  The
+ * caller gathers the kept points (types and end-of-polyline marks are unchanged, as end
+ * points survive) and builds the simulator on them.  workspace: device, 256-byte aligned,
+ * at least gd_decimate_workspace_size(n_points) bytes, used for polylines of more than
+ * 4096 points.  Asynchronous on `stream`; the library allocates nothing. */
+gd_status gd_decimate_workspace_size(int32_t n_points, size_t *bytes);
+gd_status gd_decimate(const int32_t *poly_off, int32_t n_poly, int32_t n_points, const float *x,
+                      const float *y, float min_area, uint8_t *keep, float *dir, void *workspace,
+                      size_t workspace_bytes, void *stream);
 
 /* Re-point the observation outputs (obs_ego, obs_partner, partner_mask, obs_road,
  * road_idx, lidar, lidar_hit; the other fields of `bufs` are ignored) so that the next

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libgd.so")
-SOURCES = ["gd_api.hip", "gd_build.hip", "gd_step.hip", "gd_lidar.hip", "gd_rollout.hip"]
+SOURCES = ["gd_api.hip", "gd_build.hip", "gd_step.hip", "gd_lidar.hip", "gd_rollout.hip", "gd_decimate.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -24,6 +24,8 @@ hipError_t launch_rollout_bwd_impl(const SimArgs &a, const float2 *actions, cons
 hipError_t launch_invert_actions_impl(const float *states, int T, int A, float dt, float *actions,
                                       hipStream_t s);
 constexpr int kMaxInvertSteps = 65535 * 16;  // launch chunks of 16 steps on grid axis y
+hipError_t launch_decimate_impl(const int *poly_off, int n_poly, int n_points, const float *x, const float *y,
+                                float min_area, uint8_t *keep, float *dir, void *ws, hipStream_t s);
 bool step_kernel_node(const SimArgs *a, const StepCtl *c, int waves, int bins,
                       hipKernelNodeParams &p, void **args);
 bool lidar_kernel_node(const SimArgs *a, const LidarCtl *lc, hipKernelNodeParams &p, void **args);
@@ -626,6 +628,29 @@ gd_status gd_invert_actions(gd_sim *sim, const float *states, int32_t T, float *
     hipStream_t s = (hipStream_t)stream;
     TIMED(sim, s, GD_PHASE_INVERT, launch_invert_actions_impl(states, T, A, sim->args.dt, actions, s),
           "action inversion launch");
+    return GD_OK;
+}
+
+gd_status gd_decimate_workspace_size(int32_t n_points, size_t *bytes) {
+    if (!bytes) return fail(GD_E_ARG, "bytes is NULL");
+    if (n_points < 0) return fail(GD_E_ARG, "n_points must be >= 0");
+    *bytes = decimate_ws_offset(n_points, 3);
+    return GD_OK;
+}
+
+gd_status gd_decimate(const int32_t *poly_off, int32_t n_poly, int32_t n_points, const float *x,
+                      const float *y, float min_area, uint8_t *keep, float *dir, void *workspace,
+                      size_t workspace_bytes, void *stream) {
+    if (n_poly < 0 || n_points < 0) return fail(GD_E_ARG, "n_poly and n_points must be >= 0");
+    if (!(min_area >= 0.0f) || !std::isfinite(min_area)) return fail(GD_E_ARG, "min_area must be finite and >= 0");
+    if (n_poly == 0 || n_points == 0) return GD_OK;
+    if (!poly_off || !x || !y || !keep || !dir || !workspace) return fail(GD_E_ARG, "NULL buffer");
+    if (workspace_bytes < decimate_ws_offset(n_points, 3))
+        return fail(GD_E_SIZE, "workspace of %zu bytes, %zu needed", workspace_bytes, decimate_ws_offset(n_points, 3));
+    if (((uintptr_t)workspace % 256) != 0) return fail(GD_E_ARG, "workspace must be 256-byte aligned");
+    HIP_TRY(launch_decimate_impl(poly_off, n_poly, n_points, x, y, min_area, keep, dir, workspace,
+                                 (hipStream_t)stream),
+            "decimation launch");
     return GD_OK;
 }
 

@@ -105,6 +105,13 @@ struct Layout {
 };
 Layout make_layout(int W, long long A, long long R);
 
+// Workspace of the polyline decimation: areas (f32), then predecessor and successor links
+// (i32) of every point, each region 256-byte aligned; part 3 is the total.
+inline size_t decimate_ws_offset(long long n_points, int part) {
+    const size_t region = ((size_t)n_points * 4 + 255) / 256 * 256;
+    return region * (size_t)part;
+}
+
 // launchers (return hipError_t of the launch)
 hipError_t launch_build_grid(const SimArgs &a, float cell_size, hipStream_t s);
 hipError_t launch_step(const SimArgs &a, const StepCtl &c, int waves, int bins, hipStream_t s);

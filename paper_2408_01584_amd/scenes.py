@@ -266,6 +266,32 @@ def _build_road(polys, total_points, exact_spacing=False):
     return (np.concatenate(xs), np.concatenate(ys), np.concatenate(dirs), np.concatenate(metas))
 
 
+def _build_dense_road(polys, rng, spacing, wobble, wavelength, jitter):
+    """Polylines sampled every ``spacing`` m (the paper's source maps are sampled at
+    0.1 m, Sec. 3.1) with a smooth lateral wobble (amplitude ``wobble`` m, wavelength
+    ``wavelength`` m, random phase per polyline, fading to zero at the ends) and a
+    Gaussian jitter of ``jitter`` m, so that nothing is exactly straight."""
+    xs, ys, dirs, metas = [], [], [], []
+    for typ, pts in polys:
+        L = _poly_len(pts)
+        n = max(2, int(round(L / spacing)) + 1)
+        px, py = _resample(pts, n)
+        tx, ty = np.gradient(px), np.gradient(py)
+        tn = np.maximum(np.hypot(tx, ty), 1e-12)
+        nx, ny = -ty / tn, tx / tn
+        sarc = np.linspace(0.0, L, n)
+        fade = np.minimum(1.0, np.minimum(sarc, L - sarc) / 10.0)
+        off = wobble * fade * np.sin(2 * np.pi * sarc / wavelength + rng.uniform(0, 2 * np.pi))
+        px = px + off * nx + rng.normal(0.0, jitter, n)
+        py = py + off * ny + rng.normal(0.0, jitter, n)
+        d = np.arctan2(np.diff(py), np.diff(px))
+        d = np.concatenate([d, d[-1:]])
+        m = np.full(n, typ, dtype=np.int32)
+        m[-1] |= META_LAST
+        xs.append(px); ys.append(py); dirs.append(d); metas.append(m)
+    return (np.concatenate(xs), np.concatenate(ys), np.concatenate(dirs), np.concatenate(metas))
+
+
 # --------------------------------------------------------------------------------------
 # agents
 # --------------------------------------------------------------------------------------
@@ -304,8 +330,11 @@ def _wrap(a):
     return (a + np.pi) % (2.0 * np.pi) - np.pi
 
 
-def make_world(cfg: int, w: int, n_worlds: int | None = None):
-    """Arrays of world ``w`` of configuration ``cfg`` (float64, before the float32 cast)."""
+def make_world(cfg: int, w: int, n_worlds: int | None = None, dense: dict | None = None):
+    """Arrays of world ``w`` of configuration ``cfg`` (float64, before the float32 cast).
+    ``dense`` (keys spacing, wobble, wavelength, jitter) replaces the fixed point count by
+    polylines sampled densely as in the paper's source maps (``_build_dense_road``, drawn
+    from SeedSequence(4000 + cfg)); agents and geometry are those of the plain world."""
     spec = CONFIGS[cfg]
     W = spec.worlds if n_worlds is None else n_worlds
     ss = np.random.SeedSequence(1000 + cfg).spawn(max(W, w + 1))[w]
@@ -324,7 +353,11 @@ def make_world(cfg: int, w: int, n_worlds: int | None = None):
         ax, ay, ah, sp, gx, gy = _place_agents(rng, lanes, n_agents)
     else:
         polys = _grid_geometry(rng)
-        rx, ry, rd, rm = _build_road(polys, n_road)
+        if dense is not None:
+            rng2 = np.random.Generator(np.random.PCG64(np.random.SeedSequence(4000 + cfg).spawn(max(W, w + 1))[w]))
+            rx, ry, rd, rm = _build_dense_road(polys, rng2, **dense)
+        else:
+            rx, ry, rd, rm = _build_road(polys, n_road)
         lanes = [p for t, p in polys if t == LANE]
         ax, ay, ah, sp, gx, gy = _place_agents(rng, lanes, n_agents)
         # a seeded rigid motion per world so that no two worlds share coordinates
@@ -345,10 +378,10 @@ def make_world(cfg: int, w: int, n_worlds: int | None = None):
                 road_x=rx, road_y=ry, road_dir=rd, road_meta=rm)
 
 
-def make_scene(cfg: int, worlds=None) -> Scene:
+def make_scene(cfg: int, worlds=None, dense: dict | None = None) -> Scene:
     """Scene of configuration ``cfg``.  ``worlds`` (an iterable of world indices or
     an int n meaning range(n)) selects a subset; each world is identical to the same
-    world in the full batch."""
+    world in the full batch.  ``dense``: see ``make_world``."""
     spec = CONFIGS[cfg]
     if worlds is None:
         idx = list(range(spec.worlds))
@@ -356,7 +389,7 @@ def make_scene(cfg: int, worlds=None) -> Scene:
         idx = list(range(int(worlds)))
     else:
         idx = [int(i) for i in worlds]
-    parts = [make_world(cfg, w, spec.worlds) for w in idx]
+    parts = [make_world(cfg, w, spec.worlds, dense) for w in idx]
     return assemble(cfg, parts, spec.params, world_ids=idx)
 
 

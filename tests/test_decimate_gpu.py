@@ -1,0 +1,91 @@
+"""Visvalingam-Whyatt decimation on the GPU against the oracle: keep masks bit-exact (the
+areas that decide them are binary32 with the same operation order on both sides), the
+directions of the kept points within the step tolerance, on dense road maps (polylines
+staged in LDS), on polylines longer than the LDS capacity (areas and links in the
+workspace), on degenerate polylines; then a decimated scene stepped against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from tests._parity import TOL, assert_close, teacher_forced_run
+
+pytestmark = pytest.mark.gpu
+
+DENSE = dict(spacing=0.1, wobble=0.3, wavelength=40.0, jitter=0.002)
+
+
+def _gpu(off, x, y, min_area):
+    from paper_2408_01584_amd.ingest import decimate_road
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a, dt), device="cuda")
+    keep, d = decimate_road(t(x, np.float32), t(y, np.float32), t(off, np.int32), min_area)
+    return keep.cpu().numpy(), d.cpu().numpy()
+
+
+def _compare(oracle_mod, off, x, y, min_area):
+    kg, dg = _gpu(off, x, y, min_area)
+    ko, do = oracle_mod.decimate(off, x, y, min_area)
+    assert np.array_equal(kg, ko), "keep differs at %s" % np.flatnonzero(kg != ko)[:5]
+    m = ko.astype(bool)
+    assert_close(dg[m], do[m], "dir", angle=True)
+    assert np.all(dg[~m] == 0.0)
+    return int(m.sum())
+
+
+@pytest.mark.parametrize("min_area", [0.002, 0.01, 0.2])
+def test_dense_map_matches_oracle(gpu, oracle_mod, min_area):
+    from paper_2408_01584_amd import scenes as S
+    from paper_2408_01584_amd.ingest import polyline_offsets
+    sc = S.make_scene(1, worlds=3, dense=DENSE)
+    off = polyline_offsets(sc.road_meta)
+    kept = _compare(oracle_mod, off, sc.road_x, sc.road_y, min_area)
+    print("min_area %.3f: %d of %d points kept (%.1fx)" % (min_area, kept, sc.num_road, sc.num_road / kept))
+
+
+def test_long_polylines_use_the_workspace(gpu, oracle_mod):
+    """Polylines of 4097 and 9000 points (beyond the 4096 staged in LDS) beside short ones."""
+    rng = np.random.default_rng(7)
+    lens = [4097, 5, 9000, 1, 2, 3, 4096, 64, 65]
+    xs, ys = [], []
+    for n in lens:
+        s = np.arange(n) * 0.1
+        xs.append(s + rng.normal(0, 0.003, n))
+        ys.append(0.5 * np.sin(s / 7.0) + rng.normal(0, 0.003, n))
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int32)
+    x, y = np.concatenate(xs).astype(np.float32), np.concatenate(ys).astype(np.float32)
+    for min_area in (0.0, 0.001, 0.05):
+        _compare(oracle_mod, off, x, y, min_area)
+
+
+def test_tiny_random_polylines(gpu, oracle_mod):
+    """Many short random polylines with collinear runs and repeated points (equal areas
+    and ties), one wave each."""
+    rng = np.random.default_rng(3)
+    xs, ys, off = [], [], [0]
+    for _ in range(3000):
+        n = int(rng.integers(1, 40))
+        x = rng.normal(0, 2, n).cumsum()
+        y = rng.normal(0, 2, n).cumsum()
+        if rng.random() < 0.3:
+            y[: n // 2] = 1.0
+            x[: n // 2] = np.arange(n // 2) * 0.5
+        if rng.random() < 0.2 and n > 4:
+            x[3], y[3] = x[2], y[2]
+        xs.append(x); ys.append(y); off.append(off[-1] + n)
+    x, y = np.concatenate(xs).astype(np.float32), np.concatenate(ys).astype(np.float32)
+    for min_area in (0.0, 0.5, 3.0):
+        _compare(oracle_mod, np.array(off, np.int32), x, y, min_area)
+
+
+def test_decimated_scene_steps_against_oracle(gpu, oracle_mod):
+    """Dense map -> GPU decimation -> simulator on the kept points, teacher-forced against
+    the oracle on the same decimated scene."""
+    from paper_2408_01584_amd import scenes as S
+    from paper_2408_01584_amd.ingest import decimate_scene
+    from paper_2408_01584_amd.sim import Sim
+    sc = S.make_scene(1, worlds=4, dense=DENSE)
+    dsc, keep = decimate_scene(sc, 0.01)
+    assert dsc.num_road == keep.sum() and dsc.num_road < sc.num_road / 10
+    assert (dsc.road_meta & S.META_LAST).sum() == (sc.road_meta & S.META_LAST).sum()
+    acts = S.make_actions(1, 3, dsc.num_agents)
+    st = teacher_forced_run(dsc, Sim(dsc), oracle_mod, acts, 3)
+    print("decimated scene: %d -> %d points," % (sc.num_road, dsc.num_road), st)
