@@ -43,6 +43,9 @@ def parse():
                     help="replay a HIP graph per step instead of launching the kernel directly")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
+    ap.add_argument("--ingest", action="store_true",
+                    help="time the road decimation of the headline workload's map sampled every "
+                         "0.1 m, and the step on the decimated map")
     ap.add_argument("--config", type=int, default=1, choices=(0, 1, 2, 3, 4),
                     help="1 (default): the headline workload; 0, 2, 3, 4: the secondary "
                          "workloads (latency, uneven batch, differentiable rollout, LIDAR + "
@@ -114,6 +117,9 @@ def main():
               "no exchange between GPUs, and this build measures one GPU's share (--gpus 1).",
               file=sys.stderr)
         sys.exit(2)
+    if args.ingest:
+        ingest_leg(args)
+        return
     if args.config != 1:
         secondary(args)
         return
@@ -322,6 +328,111 @@ def secondary(args):
         del sim
         torch.cuda.empty_cache()
         out["delta"] = delta_model_legs(scene, T, c)
+        if p.lidar_rays > 0:
+            out["view_cone"] = view_cone_leg(scene, T, c)
+    print(json.dumps(out), flush=True)
+
+
+def view_cone_leg(scene, T, c):
+    """The full step with the LIDAR as a 120-degree view cone of the same ray count, the
+    head of every agent turned at random before each step (the head-rotation input)."""
+    import dataclasses
+    import math
+
+    import numpy as np
+    import torch
+
+    from paper_2408_01584_amd import scenes as S
+    from paper_2408_01584_amd.sim import Sim
+
+    A = scene.num_agents
+    acts = torch.as_tensor(S.make_actions(c, T + 10, A), device="cuda")
+    heads = torch.as_tensor(np.random.default_rng(5).uniform(-1.5, 1.5, (T + 10, A)).astype(np.float32),
+                            device="cuda")
+    sim = Sim(scene, params=dataclasses.replace(scene.params, lidar_fov=math.radians(120.0)))
+    head = sim.buf["lidar_head"]
+
+    def steps(n):
+        def f():
+            for k in range(n):
+                head[:A].copy_(heads[k])
+                sim.step(acts[k])
+        return f
+    steps(10)()
+    ms = _timed(steps(T))
+    sim.close()
+    return {"fov_deg": 120.0, "rays": scene.params.lidar_rays, "ms_per_step": round(ms / T, 5),
+            "agent_steps_per_s": round(A * T / (ms / 1e3), 1),
+            "note": "includes one device copy of the head angles per step"}
+
+
+def ingest_leg(args):
+    """Road decimation at ingest (Sec. 3.1) on the headline workload's 256 worlds with the
+    road polylines sampled every 0.1 m (about 103 000 points per world, 26.4 M in all):
+    Visvalingam-Whyatt with min_area 0.01 m^2 (median of 5 launches, inputs resident),
+    then 91 steps of the simulator on the decimated map.  Latency-bound (each polyline's
+    removals are sequential); algorithmic bytes 13 per input point (x, y read; keep, dir
+    written)."""
+    import numpy as np
+    import torch
+
+    from oracle import oracle as O
+    from paper_2408_01584_amd import scenes as S
+    from paper_2408_01584_amd.ingest import decimate_road, decimate_scene, polyline_offsets
+    from paper_2408_01584_amd.sim import Sim
+
+    torch.cuda.set_device(0)
+    min_area = 0.01
+    dense = dict(spacing=0.1, wobble=0.3, wavelength=40.0, jitter=0.002)
+    print("[bench] generating the dense map", file=sys.stderr, flush=True)
+    sc = S.make_scene(1, dense=dense)
+    po = polyline_offsets(sc.road_meta)
+    dev = torch.device("cuda")
+    x = torch.as_tensor(sc.road_x, device=dev)
+    y = torch.as_tensor(sc.road_y, device=dev)
+    pot = torch.as_tensor(po, device=dev)
+    decimate_road(x, y, pot, min_area)
+    ms = _timed(lambda: decimate_road(x, y, pot, min_area))
+    dsc, keep = decimate_scene(sc, min_area)
+    n = sc.num_road
+    out = {"metric": "road points decimated/s on 1 MI355X", "unit": "points/s",
+           "value": round(n / (ms / 1e3), 1), "ms_per_launch": round(ms, 3),
+           "config": {"workload": "256 worlds of the headline map, polylines sampled every 0.1 m "
+                                  "with a 0.3 m wobble and 2 mm jitter; Visvalingam-Whyatt, "
+                                  "min_area 0.01 m^2", "points": n, "polylines": len(po) - 1,
+                      "longest_polyline": int(np.diff(po).max())},
+           "kept": int(keep.sum()), "reduction": round(n / max(int(keep.sum()), 1), 2),
+           "bound": "latency", "algorithmic_bytes_per_launch": 13 * n}
+    del x, y, pot
+    # the step on the decimated map against the fixed 4000-point map of the headline
+    A = dsc.num_agents
+    acts = torch.as_tensor(S.make_actions(1, 101, A), device=dev)
+    for name, scene in (("decimated", dsc), ("fixed_4000", S.make_scene(1))):
+        sim = Sim(scene)
+
+        def run(k0, n_steps):
+            def f():
+                for k in range(n_steps):
+                    sim.step(acts[k0 + k])
+            return f
+        run(0, 10)()
+        ms_s = _timed(run(10, 91))
+        out["step_" + name] = {"road_points_per_world": round(scene.num_road / scene.num_worlds, 1),
+                               "ms_per_step": round(ms_s / 91, 5),
+                               "agent_steps_per_s": round(A * 91 / (ms_s / 1e3), 1)}
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    # the oracle on 8 of the worlds, for context
+    sub = S.make_scene(1, worlds=8, dense=dense)
+    spo = polyline_offsets(sub.road_meta)
+    import time
+    t = time.perf_counter()
+    O.decimate(spo, sub.road_x, sub.road_y, min_area)
+    dt = time.perf_counter() - t
+    out["cpu_oracle"] = {"value": round(sub.num_road / dt, 1), "unit": "points/s",
+                         "sample": "8 worlds (%d points), %.2f s" % (sub.num_road, dt),
+                         "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))}
     print(json.dumps(out), flush=True)
 
 

@@ -10,17 +10,20 @@
 // order (no contraction).
 //
 // One wave per polyline.  The polyline's points, areas and links (a doubly linked list of
-// the surviving points) sit in LDS when it has at most kDecCap points, otherwise the
-// areas and links go to the caller's workspace and the points are read from the input.
-// Each removal is one wave-wide minimum over (area bits, index) -- areas are >= 0, so
-// their bit patterns order like the values, and removed or end points carry +inf --
-// followed by the relinking and the two area updates on one lane.
+// the surviving points) sit in LDS when it has at most kDecCap points (= 64 chunks of 64,
+// one chunk minimum per lane), otherwise the areas and links go to the caller's
+// workspace and the points are read from the input.
+// Each removal takes two wave-wide minima, of the area bits and then of the first index
+// holding that minimum -- areas are >= 0, so their bit patterns order like the values;
+// end points carry +inf and removed points a pattern above it -- followed by the
+// relinking and the two area updates on one lane.
 #include "gd_internal.h"
 
 namespace gdk {
 
 constexpr int kDecWaves = 2;     // waves (polylines in flight) per workgroup
 constexpr int kDecCap = 4096;    // points of a polyline staged in LDS (16 B each)
+static_assert(kDecCap <= 64 * 64, "one chunk minimum per lane");
 
 __device__ __forceinline__ float dec_area(const float *x, const float *y, int a, int b, int c) {
 #pragma clang fp contract(off)
@@ -30,13 +33,16 @@ __device__ __forceinline__ float dec_area(const float *x, const float *y, int a,
     return 0.5f * fabsf(p - q);
 }
 
-__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        const unsigned long long o = __shfl_xor(v, m, kWave);
-        v = o < v ? o : v;
-    }
-    return v;
+// minimum over the wave: row minima by DPP row rotations, then the four rows' minima
+// through readlane (all 64 lanes must be active)
+__device__ __forceinline__ unsigned wave_min_u32(unsigned v) {
+    v = min(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false));  // row_ror:8
+    v = min(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xf, 0xf, false));  // row_ror:4
+    v = min(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x122, 0xf, 0xf, false));  // row_ror:2
+    v = min(v, (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x121, 0xf, 0xf, false));  // row_ror:1
+    const unsigned a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+    const unsigned c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+    return min(min(a, b), min(c, d));
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -44,52 +50,117 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// area bits of a removed point: above every area, +inf (end points) and every NaN
+constexpr unsigned kRemoved = 0xffffffffu;
+
+// (area bits, index) of the first smallest area among AR[c*64 .. c*64+63] (kRemoved
+// when the chunk holds no candidate), uniform over the wave
+__device__ __forceinline__ void chunk_min(const float *AR, int n, int c, int lane, unsigned &cm, unsigned &ck) {
+    const int k = c * kWave + lane;
+    const unsigned a = k < n ? __float_as_uint(AR[k]) : kRemoved;
+    cm = wave_min_u32(a);
+    ck = wave_min_u32(a == cm ? (unsigned)k : 0xffffffffu);
+}
+
 // one polyline of n points, X/Y its coordinates, AR/PRV/NXT its areas and links (local
-// indices), keep/dir the outputs at its first point
-template <typename Link>
+// indices), keep/dir the outputs at its first point.  Removed points are marked in AR
+// only (kRemoved), so that the removal loop touches no global memory when AR and the
+// links sit in LDS; keep is written at the end.
+//
+// CHUNKED (n <= 64 * 64): lane c keeps the smallest (area, index) of the 64-point chunk
+// c in registers; a removal changes the areas of at most three points, so only their
+// chunks are rescanned (one load per lane each).  Otherwise every lane rescans its
+// strided share of the points before each removal.
+template <typename Link, bool CHUNKED>
 __device__ void vw_polyline(int n, int lane, const float *X, const float *Y, float *AR, Link *PRV, Link *NXT,
                             float min_area, uint8_t *keep, float *dir) {
     for (int k = lane; k < n; k += kWave) {
         PRV[k] = (Link)(k - 1);
         NXT[k] = (Link)(k + 1);
-        keep[k] = 1;
         AR[k] = (k > 0 && k < n - 1) ? dec_area(X, Y, k - 1, k, k + 1) : INFINITY;
     }
     wave_sync();
-    for (;;) {
-        unsigned long long best = ~0ull;
-        for (int k = lane; k < n; k += kWave) {
-            const unsigned long long key = ((unsigned long long)__float_as_uint(AR[k]) << 32) | (unsigned)k;
-            best = key < best ? key : best;
+    const unsigned lim = __float_as_uint(min_area);  // areas >= 0 order like their bits
+    unsigned bb = kRemoved, bk = 0xffffffffu;         // this lane's candidate
+    if (CHUNKED) {
+        const int nch = (n + kWave - 1) / kWave;
+        for (int c = 0; c < nch; c++) {
+            unsigned cm, ck;
+            chunk_min(AR, n, c, lane, cm, ck);
+            if (lane == c) {
+                bb = cm;
+                bk = ck;
+            }
         }
-        best = wave_min_u64(best);
-        const float ba = __uint_as_float((unsigned)(best >> 32));
-        if (!(ba < min_area)) break;  // also ends the loop when only end points remain
-        const int q = (int)(unsigned)best;
+    }
+    for (;;) {
+        if (!CHUNKED) {
+            bb = kRemoved;
+            bk = 0xffffffffu;
+#pragma unroll 8
+            for (int k = lane; k < n; k += kWave) {
+                const unsigned a = __float_as_uint(AR[k]);
+                if (a < bb) {
+                    bb = a;
+                    bk = (unsigned)k;
+                }
+            }
+        }
+        const unsigned m = wave_min_u32(bb);
+        if (!(m < lim)) break;  // also ends the loop when only end points remain
+        const int q = (int)wave_min_u32(bb == m ? bk : 0xffffffffu);
+        int p = 0, r = 0;
         if (lane == 0) {
             // the Link round trip keeps -1 (no predecessor) only for the first point,
             // which is never removed, so p and r are valid indices here
-            const int p = (int)PRV[q], r = (int)NXT[q];
+            p = (int)PRV[q];
+            r = (int)NXT[q];
             NXT[p] = (Link)r;
             PRV[r] = (Link)p;
-            AR[q] = INFINITY;
-            keep[q] = 0;
+            AR[q] = __uint_as_float(kRemoved);
             if (p > 0) AR[p] = dec_area(X, Y, (int)PRV[p], p, r);
             if (r < n - 1) AR[r] = dec_area(X, Y, p, r, (int)NXT[r]);
         }
         wave_sync();
+        if (CHUNKED) {
+            p = __builtin_amdgcn_readlane(p, 0);
+            r = __builtin_amdgcn_readlane(r, 0);
+            const int c0 = q / kWave, c1 = p / kWave, c2 = r / kWave;
+            unsigned cm, ck;
+            chunk_min(AR, n, c0, lane, cm, ck);
+            if (lane == c0) {
+                bb = cm;
+                bk = ck;
+            }
+            if (c1 != c0) {
+                chunk_min(AR, n, c1, lane, cm, ck);
+                if (lane == c1) {
+                    bb = cm;
+                    bk = ck;
+                }
+            }
+            if (c2 != c0 && c2 != c1) {
+                chunk_min(AR, n, c2, lane, cm, ck);
+                if (lane == c2) {
+                    bb = cm;
+                    bk = ck;
+                }
+            }
+        }
     }
     for (int k = lane; k < n; k += kWave) {
+        const bool kept = __float_as_uint(AR[k]) != kRemoved;
         float d = 0.0f;
-        if (keep[k]) {
+        if (kept) {
             const int j = (int)NXT[k];
             if (j < n) {
                 d = atan2f(Y[j] - Y[k], X[j] - X[k]);
             } else if (k > 0) {
-                const int p = (int)PRV[k];
-                d = atan2f(Y[k] - Y[p], X[k] - X[p]);
+                const int pk = (int)PRV[k];
+                d = atan2f(Y[k] - Y[pk], X[k] - X[pk]);
             }
         }
+        keep[k] = kept ? 1 : 0;
         dir[k] = d;
     }
 }
@@ -120,9 +191,10 @@ __global__ __launch_bounds__(kDecWaves * kWave) void k_decimate(const int *__res
                 sy[k] = gy[s + k];
             }
             wave_sync();
-            vw_polyline<unsigned short>(n, lane, sx, sy, sa, sp, sn, min_area, keep + s, dir + s);
+            vw_polyline<unsigned short, true>(n, lane, sx, sy, sa, sp, sn, min_area, keep + s, dir + s);
         } else {
-            vw_polyline<int>(n, lane, gx + s, gy + s, g_area + s, g_prv + s, g_nxt + s, min_area, keep + s, dir + s);
+            vw_polyline<int, false>(n, lane, gx + s, gy + s, g_area + s, g_prv + s, g_nxt + s, min_area, keep + s,
+                                    dir + s);
         }
         wave_sync();
     }
