@@ -16,6 +16,9 @@
  *   - goal reached within a configurable distance, reward 1 (+ optional collision
  *     penalty), termination on goal (optionally on collision), removal after the goal
  *                                                 (Sec. 3.2 "Rewards", "Termination")
+ *   - agent classes (pedestrians may cross road edges) and the "all nontrivial"
+ *     initialisation: agents that start near their goal are parked obstacles, not
+ *     controlled                         (Sec. 3.2 "Termination", "Sharp edges")
  *   - radius-filter observations in the agent's relative frame: partner states and the
  *     nearest road points within the radius                (Fig. 1; Sec. 3.2 "Sensor modalities")
  *   - planar LIDAR against road edges and agent boxes, as a full ring or as a view cone
@@ -48,6 +51,9 @@
 #define OR_DONE 8u
 #define OR_ALIVE 16u
 #define OR_VISIBLE 32u
+#define OR_STATIC 64u /* in the scene as an obstacle, never controlled */
+
+#define OR_CLASS_PEDESTRIAN 2
 
 #define OR_AUTO_RESET 1u
 #define OR_TERM_ON_COLLISION 2u
@@ -65,6 +71,7 @@ typedef struct {
     double dt, obs_radius, goal_radius, v_max, lidar_range, collision_penalty;
     int32_t model; /* OR_MODEL_BICYCLE or OR_MODEL_DELTA */
     double lidar_fov; /* 0: rays around the full circle; (0, 2 pi]: view cone of this width */
+    double min_goal_dist; /* > 0: agents starting within it of their goal are not controlled */
 } or_config;
 
 #define OR_MODEL_BICYCLE 0
@@ -86,6 +93,8 @@ typedef struct {
     int32_t *t;                                    /* [W] */
     const double *head;                            /* [A] head angle of the view cone
                                                       (rad, from the heading); NULL = 0 */
+    const uint8_t *cls;                            /* [A] agent class (0 vehicle, 1 cyclist,
+                                                      2 pedestrian); NULL = vehicles */
 } or_batch;
 
 typedef struct {
@@ -284,7 +293,9 @@ static int is_edge_segment(const int32_t *meta, int k) {
     return (meta[k] & 0xff) == OR_TYPE_EDGE && !(meta[k] & OR_META_LAST);
 }
 
-/* collision flags of the alive agents of world w (post-dynamics state) */
+/* collision flags of the alive agents of world w (post-dynamics state): against the other
+   alive agents and the parked (static) ones, and, except for pedestrians, against the
+   road edges */
 static void collide_world(const or_batch *b, int w, uint8_t *coll, uint8_t *band) {
     int a0 = b->agent_off[w], a1 = b->agent_off[w + 1];
     int r0 = b->road_off[w], r1 = b->road_off[w + 1];
@@ -293,12 +304,13 @@ static void collide_world(const or_batch *b, int w, uint8_t *coll, uint8_t *band
         if (!(b->flags[i] & OR_ALIVE)) continue;
         double bi[5] = {b->x[i], b->y[i], b->yaw[i], b->len[i], b->wid[i]};
         for (int j = a0; j < a1; j++) {
-            if (j == i || !(b->flags[j] & OR_ALIVE)) continue;
+            if (j == i || !(b->flags[j] & (OR_ALIVE | OR_STATIC))) continue;
             double bj[5] = {b->x[j], b->y[j], b->yaw[j], b->len[j], b->wid[j]};
             double sep = or_box_box_sep(bi, bj);
             if (sep < 0.0) coll[i - a0] |= OR_COLL_AGENT;
             if (fabs(sep) < OR_BAND && band) band[i] |= 1;
         }
+        if (b->cls && b->cls[i] == OR_CLASS_PEDESTRIAN) continue;
         for (int k = r0; k < r1 - 1; k++) {
             if (!is_edge_segment(b->rmeta, k)) continue;
             double sep = or_box_seg_sep(bi, b->rx[k], b->ry[k], b->rx[k + 1], b->ry[k + 1]);
@@ -367,7 +379,8 @@ static void obs_world(const or_batch *b, const or_config *c, int w, const or_out
     double R = c->obs_radius;
     for (int i = a0; i < a1; i++) {
         int l = i - a0;
-        int vis = (b->flags[i] & OR_VISIBLE) != 0;
+        /* parked agents are seen by others but observe nothing themselves */
+        int vis = (b->flags[i] & OR_VISIBLE) && !(b->flags[i] & OR_STATIC);
         double *ego = o->ego + (int64_t)i * 8;
         int64_t sb = slot_base(b, c, w, l);
         double *road = o->road + (int64_t)i * K * 4;
@@ -530,15 +543,27 @@ void or_collide(const or_batch *b, uint8_t *coll_out, uint8_t *band) {
     }
 }
 
-/* Reset worlds (mask NULL = all): state <- snapshot, all agents alive and visible,
-   t <- 0. */
-static void reset_world(const or_batch *b, int w) {
+/* Flags of agent i at the start of an episode: alive and visible, or, with the "all
+   nontrivial" initialisation, visible and static when it starts within min_goal_dist of
+   its goal (binary32 key, inclusive; band bit 2 within 1e-4 m of the threshold). */
+static uint8_t start_flags(const or_batch *b, const or_config *c, int i, uint8_t *band) {
+    if (c->min_goal_dist > 0.0) {
+        float d2 = key32((float)b->x[i], (float)b->y[i], (float)b->gx[i], (float)b->gy[i]);
+        double d = hypot(b->gx[i] - b->x[i], b->gy[i] - b->y[i]);
+        if (band && fabs(d - c->min_goal_dist) < OR_BAND) band[i] |= 2;
+        if (d2 <= r2_32(c->min_goal_dist)) return OR_VISIBLE | OR_STATIC;
+    }
+    return OR_ALIVE | OR_VISIBLE;
+}
+
+/* Reset worlds (mask NULL = all): state <- snapshot, start flags, t <- 0. */
+static void reset_world(const or_batch *b, const or_config *c, int w, uint8_t *band) {
     for (int i = b->agent_off[w]; i < b->agent_off[w + 1]; i++) {
         b->x[i] = b->snap_x[i];
         b->y[i] = b->snap_y[i];
         b->yaw[i] = b->snap_yaw[i];
         b->v[i] = b->snap_v[i];
-        b->flags[i] = OR_ALIVE | OR_VISIBLE;
+        b->flags[i] = start_flags(b, c, i, band);
     }
     b->t[w] = 0;
 }
@@ -546,7 +571,7 @@ static void reset_world(const or_batch *b, int w) {
 void or_reset(const or_batch *b, const or_config *c, const uint8_t *mask, const or_outputs *o) {
     for (int w = 0; w < b->W; w++)
         if (!mask || mask[w]) {
-            reset_world(b, w);
+            reset_world(b, c, w, o ? o->band : NULL);
             if (o && o->reward)
                 for (int i = b->agent_off[w]; i < b->agent_off[w + 1]; i++) o->reward[i] = 0.0;
             if (o && o->world_done) o->world_done[w] = 0;
@@ -591,6 +616,10 @@ static void step_world(const or_batch *b, const or_config *c, int w, const doubl
                 out |= OR_ALIVE;
                 any_alive = 1;
             }
+        } else if (f & OR_STATIC) {
+            /* a parked agent stays in place, earns nothing and never finishes */
+            out = OR_VISIBLE | OR_STATIC;
+            done = 0;
         }
         if (done) out |= OR_DONE;
         b->flags[i] = out;
@@ -606,7 +635,7 @@ static void step_world(const or_batch *b, const or_config *c, int w, const doubl
             b->y[i] = b->snap_y[i];
             b->yaw[i] = b->snap_yaw[i];
             b->v[i] = b->snap_v[i];
-            b->flags[i] = keep | OR_ALIVE | OR_VISIBLE;
+            b->flags[i] = keep | start_flags(b, c, i, o->band);
         }
         b->t[w] = 0;
     } else {

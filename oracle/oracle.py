@@ -19,7 +19,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "gd_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-COLL_AGENT, COLL_EDGE, GOAL, DONE, ALIVE, VISIBLE = 1, 2, 4, 8, 16, 32
+COLL_AGENT, COLL_EDGE, GOAL, DONE, ALIVE, VISIBLE, STATIC = 1, 2, 4, 8, 16, 32, 64
+VEHICLE, CYCLIST, PEDESTRIAN = 0, 1, 2
 AUTO_RESET, TERM_ON_COLLISION = 1, 2
 MODEL_BICYCLE, MODEL_DELTA = 0, 1
 INV_MIN_DIST = 1e-3  # the inversion's distance threshold (m), as in gd_oracle.c
@@ -52,14 +53,14 @@ class Config(C.Structure):
                 ("lidar_rays", C.c_int32), ("flags", C.c_uint32), ("dt", C.c_double),
                 ("obs_radius", C.c_double), ("goal_radius", C.c_double), ("v_max", C.c_double),
                 ("lidar_range", C.c_double), ("collision_penalty", C.c_double),
-                ("model", C.c_int32), ("lidar_fov", C.c_double)]
+                ("model", C.c_int32), ("lidar_fov", C.c_double), ("min_goal_dist", C.c_double)]
 
 
 class Batch(C.Structure):
     _fields_ = [("W", C.c_int32), ("agent_off", C.c_void_p), ("road_off", C.c_void_p)] + \
         [(n, C.c_void_p) for n in ("x", "y", "yaw", "v", "len", "wid", "gx", "gy", "snap_x",
                                    "snap_y", "snap_yaw", "snap_v", "rx", "ry", "rdir", "rmeta",
-                                   "flags", "t", "head")]
+                                   "flags", "t", "head", "cls")]
 
 
 class Outputs(C.Structure):
@@ -95,7 +96,8 @@ def config_from_params(p) -> Config:
     flags = (AUTO_RESET if p.auto_reset else 0) | (TERM_ON_COLLISION if p.terminate_on_collision else 0)
     return Config(p.top_k, p.partners, p.episode_len, p.lidar_rays, flags, p.dt, p.obs_radius,
                   p.goal_radius, p.v_max, p.lidar_range, p.collision_penalty,
-                  getattr(p, "dynamics", MODEL_BICYCLE), getattr(p, "lidar_fov", 0.0))
+                  getattr(p, "dynamics", MODEL_BICYCLE), getattr(p, "lidar_fov", 0.0),
+                  getattr(p, "min_goal_dist", 0.0))
 
 
 def partner_slots(agent_off: np.ndarray, partners: int) -> int:
@@ -184,12 +186,16 @@ class OracleSim:
         self.W = len(self.agent_off) - 1
         self.A = int(self.agent_off[-1])
         self.flags = np.full(self.A, ALIVE | VISIBLE, dtype=np.uint8)
+        cls = getattr(scene, "agent_class", None)
+        self.cls = None if cls is None else np.ascontiguousarray(cls, dtype=np.uint8).copy()
         self.head = np.zeros(self.A)  # view-cone head angles (rad, from the heading)
         self.t = np.zeros(self.W, dtype=np.int32)
         p = self.params
         self.K, self.N = p.top_k, p.lidar_rays
         self.S = partner_slots(self.agent_off, p.partners)
         self._alloc_outputs()
+        if getattr(p, "min_goal_dist", 0.0) > 0.0:  # start flags of the first episode
+            lib().or_reset(C.byref(self._batch()), C.byref(self.cfg), None, None)
 
     def _alloc_outputs(self):
         A, K, N, S = self.A, self.K, self.N, self.S
@@ -209,6 +215,7 @@ class OracleSim:
         b.rx, b.ry, b.rdir, b.rmeta = _p(self.rx), _p(self.ry), _p(self.rdir), _p(self.rmeta)
         b.flags, b.t = _p(self.flags), _p(self.t)
         b.head = _p(self.head)
+        b.cls = _p(self.cls)
         self._keep = b
         return b
 

@@ -66,6 +66,7 @@ class SimParams:
     terminate_on_collision: bool = False
     dynamics: int = 0  # 0: bicycle model (App. B); 1: simplified model (Sec. 3.2 "Dynamics")
     lidar_fov: float = 0.0  # 0: LIDAR rays around the full circle; > 0: view-cone width (rad)
+    min_goal_dist: float = 0.0  # > 0: agents starting within it of their goal are parked
 
 
 @dataclass(frozen=True)
@@ -111,6 +112,7 @@ class Scene:
     road_dir: np.ndarray
     road_meta: np.ndarray
     extra: dict = field(default_factory=dict)
+    agent_class: np.ndarray | None = None  # uint8 [A]: 0 vehicle, 1 cyclist, 2 pedestrian
 
     @property
     def num_worlds(self) -> int:
