@@ -64,6 +64,15 @@ typedef enum {
 #define GD_FLAG_DONE 8u
 #define GD_FLAG_ALIVE 16u
 #define GD_FLAG_VISIBLE 32u
+#define GD_FLAG_STATIC 64u   /* parked: in the scene as an obstacle, never controlled (see
+                                gd_config.min_goal_dist) */
+
+/* ---- agent classes (gd_buffers.agent_class) ------------------------------------------
+ * Cars and cyclists collide with road edges; pedestrians may cross them (Sec. 3.2
+ * "Termination").  Classes change nothing else. */
+#define GD_CLASS_VEHICLE 0
+#define GD_CLASS_CYCLIST 1
+#define GD_CLASS_PEDESTRIAN 2
 
 /* ---- gd_config.flags ---------------------------------------------------------------- */
 #define GD_AUTO_RESET 1u              /* finished worlds restart inside gd_step */
@@ -129,6 +138,14 @@ typedef struct {
                                   a view cone of this width (rad) turned by the per-agent
                                   head angle gd_buffers.lidar_head (Sec. 3.2 "Sensor
                                   modalities") */
+    float min_goal_dist;       /* the "all nontrivial" initialisation (Sec. 3.2 "Sharp
+                                  edges", 2 m in the paper): > 0 parks every agent that
+                                  starts within this distance (m, inclusive, binary32 key as
+                                  the goal test) of its goal -- GD_FLAG_VISIBLE |
+                                  GD_FLAG_STATIC: it stays at its initial pose, is observed
+                                  and collided with by the others, earns no reward, has no
+                                  observation of its own and does not keep its world
+                                  running; 0 = every agent is controlled */
 } gd_config;
 
 typedef struct {
@@ -156,6 +173,7 @@ typedef struct {
     const float *lidar_head;   /* [A] head angle of the view cone from the heading (rad),
                                   written by the caller before each step (the head-rotation
                                   action); read only when lidar_fov > 0; NULL = 0 */
+    const uint8_t *agent_class; /* [A] GD_CLASS_*; NULL = all vehicles */
     void *workspace;           /* device scratch of at least workspace_bytes */
     size_t workspace_bytes;
 } gd_buffers;
@@ -182,7 +200,8 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off,
                     gd_sim **out);
 
 /* Reset the worlds selected by the device mask [W] (NULL = all) to the snapshot: state,
- * flags = ALIVE|VISIBLE, t = 0, reward = 0, world_done = 0; recompute observations. */
+ * flags = ALIVE|VISIBLE (VISIBLE|STATIC for agents parked by min_goal_dist), t = 0,
+ * reward = 0, world_done = 0; recompute observations. */
 gd_status gd_reset(gd_sim *sim, const uint8_t *world_mask, void *stream);
 
 /* One full step for all worlds (Sec. 3.2; App. B):
@@ -193,11 +212,13 @@ gd_status gd_reset(gd_sim *sim, const uint8_t *world_mask, void *stream);
  *      v = clip(v + a dt, +-v_max).  GD_DYN_DELTA (Sec. 3.2 "Dynamics"), actions
  *      (accel m/s^2, curvature command s 1/m): d = v dt + a dt^2/2, x += d cos(yaw),
  *      y += d sin(yaw), yaw += s d, v += a dt (no clip, independent of the length);
- *   2. collision flags among alive agents (oriented boxes) and against road-edge
- *      segments, on the new state;
+ *   2. collision flags of the alive agents, on the new state: against the other alive
+ *      and the parked agents (oriented boxes) and, except for pedestrians, against the
+ *      road-edge segments;
  *   3. goal (|p - g| <= goal_radius), reward = [goal] - penalty [collided], done =
  *      goal or (terminate-on-collision and collided) or t + 1 >= episode_len; done
  *      agents stay VISIBLE for this observation and stop being ALIVE;
+ *      parked agents keep VISIBLE|STATIC, reward 0;
  *   4. world_done = no agent ALIVE or t + 1 >= episode_len; with GD_AUTO_RESET such
  *      worlds return to the snapshot (t = 0) and the observation is the new episode's;
  *   5. observations of the resulting state (as gd_obs).
@@ -205,7 +226,8 @@ gd_status gd_reset(gd_sim *sim, const uint8_t *world_mask, void *stream);
 gd_status gd_step(gd_sim *sim, const float *actions, void *stream);
 
 /* Observations of the current state (Fig. 1; Sec. 3.2 "Sensor modalities"), for every
- * VISIBLE agent (others get zeros, masks 0, indices -1):
+ * VISIBLE agent that is not parked (others get zeros, masks 0, indices -1); parked agents
+ * are observed by the others (partners, LIDAR) like any VISIBLE agent:
  *   ego    : speed, length, width, goal in the ego frame, the collision flags of the
  *            observed state (0 when t = 0), 1;
  *   partner: each other VISIBLE agent of the world with |p_j - p_i| <= obs_radius, in

@@ -144,6 +144,8 @@ static gd_status check_config(const gd_config *c, const int32_t *h_agent_off,
         return fail(GD_E_ARG, "obs_road must be GD_ROAD_AUTO, GD_ROAD_LDS or GD_ROAD_GLOBAL");
     if (!(c->lidar_fov == 0.0f || (c->lidar_fov >= 1e-4f && c->lidar_fov <= 6.2831855f)))
         return fail(GD_E_ARG, "lidar_fov must be 0 or in [1e-4, 2 pi]");
+    if (!(c->min_goal_dist >= 0.0f) || !std::isfinite(c->min_goal_dist))
+        return fail(GD_E_ARG, "min_goal_dist must be finite and >= 0");
     if (!(c->dynamics == GD_DYN_BICYCLE || c->dynamics == GD_DYN_DELTA))
         return fail(GD_E_ARG, "dynamics must be GD_DYN_BICYCLE or GD_DYN_DELTA");
     const int W = c->num_worlds;
@@ -433,6 +435,10 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
         volatile float gr = cfg->goal_radius;
         volatile float g2 = gr * gr;
         a.goal_r2 = g2;
+        volatile float md = cfg->min_goal_dist;
+        volatile float m2 = md * md;
+        a.park = cfg->min_goal_dist > 0.0f ? 1 : 0;
+        a.park_r2 = m2;
     }
     a.vmax = cfg->v_max;
     a.lidar_range = cfg->lidar_range;
@@ -460,6 +466,7 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
     a.lidar = b->lidar;
     a.lidar_hit = b->lidar_hit;
     a.head = b->lidar_head;
+    a.cls = b->agent_class;
     a.reward = b->reward;
     a.fl = b->flags;
     a.world_done = b->world_done;

@@ -47,6 +47,9 @@ struct SimArgs {
     float *lidar;
     int *lidar_hit;
     const float *head;  // [A] view-cone head angles, NULL = 0
+    const uint8_t *cls; // [A] agent classes, NULL = all vehicles
+    int park;           // 1: agents starting within min_goal_dist of their goal are parked
+    float park_r2;      // binary32 square of min_goal_dist
     float *reward;
     uint8_t *fl;
     uint8_t *world_done;

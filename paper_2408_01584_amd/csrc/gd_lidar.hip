@@ -222,7 +222,8 @@ __global__ __launch_bounds__(kLidarMaxWaves * kWave) void k_lidar(SimArgs a, Lid
         const int ai = a0 + l;
         float *out = a.lidar + (size_t)ai * N;
         int *hit = a.lidar_hit + (size_t)ai * N;
-        if (!(__builtin_amdgcn_readfirstlane(sf[l]) & GD_FLAG_VISIBLE)) {
+        const int fl_l = __builtin_amdgcn_readfirstlane(sf[l]);
+        if (!(fl_l & GD_FLAG_VISIBLE) || (fl_l & GD_FLAG_STATIC)) {  // parked agents observe nothing
             for (int k = lane; k < N; k += kWave) {
                 out[k] = 0.0f;
                 hit[k] = 0;

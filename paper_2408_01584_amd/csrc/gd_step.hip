@@ -370,13 +370,15 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             };
             for (int i = wid; i < n; i = next_coll()) {
                 if (!(wave_uniform(sf[i]) & GD_FLAG_ALIVE)) continue;
+                // pedestrians may cross road edges (Sec. 3.2 "Termination")
+                const bool ped = a.cls && a.cls[a0 + i] == GD_CLASS_PEDESTRIAN;
                 const float xi = wave_uniform(sx[i]), yi = wave_uniform(sy[i]);
                 const float ci = wave_uniform(sc[i]), si = wave_uniform(ss[i]);
                 const float Li = wave_uniform(sL[i]), Wi = wave_uniform(sW[i]);
                 const float di = sqrtf(Li * Li + Wi * Wi);
                 bool ha = false;
                 for (int j = lane; j < n; j += kWave) {
-                    if (j == i || !(sf[j] & GD_FLAG_ALIVE)) continue;
+                    if (j == i || !(sf[j] & (GD_FLAG_ALIVE | GD_FLAG_STATIC))) continue;
                     const float dx = sx[j] - xi, dy = sy[j] - yi;
                     const float rr = 0.5f * (di + sqrtf(sL[j] * sL[j] + sW[j] * sW[j])) + 1e-3f;
                     if (dx * dx + dy * dy > rr * rr) continue;
@@ -394,7 +396,7 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
                 const int cy1 = cell_coord(yi + ey + m, g.oy, g.inv_cs, g.ny);
                 // the cells' segment ranges of each row, concatenated (lane = row), so that
                 // the segments of all rows fill the lanes together
-                const int nre = cy1 - cy0 + 1;  // at most kGridAxis
+                const int nre = ped ? 0 : cy1 - cy0 + 1;  // at most kGridAxis
                 int e0 = 0, e1 = 0;
                 if (lane < nre) {
                     e0 = ecs[(cy0 + lane) * g.nx + cx0];
@@ -445,6 +447,10 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
                     out |= GD_FLAG_ALIVE;
                     any = 1;
                 }
+            } else if (f & GD_FLAG_STATIC) {
+                // a parked agent stays in place, earns nothing and never finishes
+                out = GD_FLAG_VISIBLE | GD_FLAG_STATIC;
+                done = false;
             }
             if (done) out |= GD_FLAG_DONE;
             scoll[i] = out;  // the transition's flags
@@ -487,7 +493,10 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             const int keep = keep_outcome ? (scoll[i] & (GD_FLAG_COLL_AGENT | GD_FLAG_COLL_EDGE |
                                                          GD_FLAG_GOAL | GD_FLAG_DONE))
                                           : 0;
-            const int f = keep | GD_FLAG_ALIVE | GD_FLAG_VISIBLE;
+            // "all nontrivial" initialisation: agents that start within min_goal_dist of
+            // their goal are parked
+            const bool parked = a.park && key32(s0.x, s0.y, sgx[i], sgy[i]) <= a.park_r2;
+            const int f = keep | (parked ? (int)(GD_FLAG_VISIBLE | GD_FLAG_STATIC) : (int)(GD_FLAG_ALIVE | GD_FLAG_VISIBLE));
             sf[i] = f;
             a.fl[gi] = (uint8_t)f;
             if (mode == kModeReset) a.reward[gi] = 0.0f;
@@ -520,7 +529,7 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
         const int gi = a0 + i;
         const int f = sf[i];
         float4 e0 = make_float4(0.f, 0.f, 0.f, 0.f), e1 = e0;
-        if (f & GD_FLAG_VISIBLE) {
+        if ((f & GD_FLAG_VISIBLE) && !(f & GD_FLAG_STATIC)) {
             const float gdx = sgx[i] - sx[i], gdy = sgy[i] - sy[i];
             e0 = make_float4(sv[i], sL[i], sW[i], sc[i] * gdx + ss[i] * gdy);
             e1 = make_float4(-ss[i] * gdx + sc[i] * gdy,
@@ -552,7 +561,8 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     };
     for (int l = wid; l < n; l = next_agent()) {
         const int ai = a0 + l;
-        const bool vis = (wave_uniform(sf[l]) & GD_FLAG_VISIBLE) != 0;
+        const int fl_l = wave_uniform(sf[l]);
+        const bool vis = (fl_l & GD_FLAG_VISIBLE) && !(fl_l & GD_FLAG_STATIC);  // observer
         const float px = wave_uniform(sx[l]), py = wave_uniform(sy[l]), yaw = wave_uniform(syaw[l]);
         const float csy = wave_uniform(sc[l]), sny = wave_uniform(ss[l]);
 

@@ -17,6 +17,8 @@ STATUS_NAMES = {0: "GD_OK", -1: "GD_E_ARG", -2: "GD_E_SIZE", -3: "GD_E_HIP", -4:
                 -5: "GD_E_NONFINITE", -6: "GD_E_UNSUPPORTED"}
 
 GD_FLAG_COLL_AGENT, GD_FLAG_COLL_EDGE, GD_FLAG_GOAL, GD_FLAG_DONE, GD_FLAG_ALIVE, GD_FLAG_VISIBLE = 1, 2, 4, 8, 16, 32
+GD_FLAG_STATIC = 64
+GD_CLASS_VEHICLE, GD_CLASS_CYCLIST, GD_CLASS_PEDESTRIAN = 0, 1, 2
 GD_AUTO_RESET, GD_TERMINATE_ON_COLLISION, GD_CHECK_FINITE, GD_USE_GRAPH = 1, 2, 4, 8
 
 ENTRY_POINTS = ("gd_partner_slots", "gd_workspace_size", "gd_create", "gd_reset", "gd_step",
@@ -44,13 +46,13 @@ class gd_config(C.Structure):
                 ("v_max", C.c_float), ("lidar_range", C.c_float), ("collision_penalty", C.c_float),
                 ("cell_size", C.c_float), ("obs_waves", C.c_int32), ("obs_bins", C.c_int32),
                 ("obs_cands", C.c_int32), ("obs_road", C.c_int32), ("dynamics", C.c_int32),
-                ("lidar_fov", C.c_float)]
+                ("lidar_fov", C.c_float), ("min_goal_dist", C.c_float)]
 
 
 _BUF_FIELDS = ("agent_off", "road_off", "x", "y", "yaw", "speed", "length", "width", "goal_x",
                "goal_y", "road_x", "road_y", "road_dir", "road_meta", "obs_ego", "obs_partner",
                "partner_mask", "obs_road", "road_idx", "lidar", "lidar_hit", "reward", "flags",
-               "world_done", "t", "lidar_head", "workspace")
+               "world_done", "t", "lidar_head", "agent_class", "workspace")
 
 
 class gd_buffers(C.Structure):

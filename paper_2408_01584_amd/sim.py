@@ -40,6 +40,7 @@ def config_from_params(p, num_worlds: int, graph: bool = False, check_finite: bo
     c.obs_road = obs_road
     c.dynamics = getattr(p, "dynamics", G.GD_DYN_BICYCLE)
     c.lidar_fov = getattr(p, "lidar_fov", 0.0)
+    c.min_goal_dist = getattr(p, "min_goal_dist", 0.0)
     return c
 
 
@@ -90,6 +91,9 @@ class Sim:
         b["world_done"] = torch.zeros(W, dtype=torch.uint8, device=dev)
         b["t"] = torch.zeros(W, dtype=torch.int32, device=dev)
         b["lidar_head"] = torch.zeros(max(A, 1), dtype=torch.float32, device=dev)  # head angles
+        cls = getattr(scene, "agent_class", None)
+        b["agent_class"] = None if cls is None else \
+            torch.as_tensor(np.ascontiguousarray(cls, dtype=np.uint8), device=dev)
         b["workspace"] = torch.empty(ws + 256, dtype=torch.uint8, device=dev)
         self.buf = b
         bufs = G.gd_buffers()
@@ -97,7 +101,7 @@ class Sim:
             if name == "workspace":
                 continue
             t = b[name]
-            setattr(bufs, name, t.data_ptr())
+            setattr(bufs, name, None if t is None else t.data_ptr())
         if N == 0:
             bufs.lidar = None
             bufs.lidar_hit = None

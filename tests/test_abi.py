@@ -48,10 +48,10 @@ def test_struct_layout_matches_header(G):
 #include <stddef.h>
 #include "gd.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(gd_config), offsetof(gd_config, cell_size),
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(gd_config), offsetof(gd_config, cell_size),
          offsetof(gd_config, obs_cands), offsetof(gd_config, obs_road),
-         offsetof(gd_config, dynamics), offsetof(gd_config, lidar_fov), sizeof(gd_buffers),
-         offsetof(gd_buffers, lidar_head),
+         offsetof(gd_config, dynamics), offsetof(gd_config, lidar_fov), offsetof(gd_config, min_goal_dist),
+         sizeof(gd_buffers), offsetof(gd_buffers, lidar_head), offsetof(gd_buffers, agent_class),
          offsetof(gd_buffers, t), offsetof(gd_buffers, workspace_bytes));
   return 0;
 }'''
@@ -63,7 +63,8 @@ int main(void) {
         vals = [int(v) for v in subprocess.check_output([exe], text=True).split()]
     want = [C.sizeof(G.gd_config), G.gd_config.cell_size.offset, G.gd_config.obs_cands.offset,
             G.gd_config.obs_road.offset, G.gd_config.dynamics.offset, G.gd_config.lidar_fov.offset,
-            C.sizeof(G.gd_buffers), G.gd_buffers.lidar_head.offset, G.gd_buffers.t.offset,
+            G.gd_config.min_goal_dist.offset, C.sizeof(G.gd_buffers), G.gd_buffers.lidar_head.offset,
+            G.gd_buffers.agent_class.offset, G.gd_buffers.t.offset,
             G.gd_buffers.workspace_bytes.offset]
     assert vals == want
 
@@ -100,7 +101,7 @@ def test_host_side_sizes(G):
     ("episode_len", 0, -1), ("dt", 0.0, -1), ("obs_radius", -1.0, -1), ("v_max", 0.0, -1),
     ("obs_waves", 3, -1), ("obs_bins", 100, -1), ("lidar_rays", 2000, -2), ("cell_size", -1.0, -1),
     ("obs_road", 3, -1), ("dynamics", 2, -1), ("dynamics", -1, -1), ("lidar_fov", -0.5, -1),
-    ("lidar_fov", 1e-6, -1), ("lidar_fov", 7.0, -1),
+    ("lidar_fov", 1e-6, -1), ("lidar_fov", 7.0, -1), ("min_goal_dist", -1.0, -1),
 ])
 def test_config_validation(G, field, value, status):
     ao = np.array([0, 4, 6], np.int32)
