@@ -483,8 +483,6 @@ def delta_model_legs(scene, T, c):
 def cpu_baseline_decimation(dense, min_area):
     """The oracle's decimation (plain C, OpenMP over polylines) on a bounded sample of the
     dense map: 8 of its 256 worlds."""
-    import time
-
     from oracle import oracle as O
     from paper_2408_01584_amd import scenes as S
     from paper_2408_01584_amd.ingest import polyline_offsets
