@@ -73,3 +73,27 @@ def test_pedestrian_crosses_edge(gpu, oracle_mod):
     o = O.OracleSim(sc).step(np.zeros((4, 2)))
     assert np.array_equal(g["flags"], o["flags"])
     assert not g["flags"][2] & O.COLL_EDGE and g["flags"][2] & O.COLL_AGENT and g["flags"][0] & O.COLL_EDGE
+
+
+def test_graph_mode_with_every_option(gpu):
+    """The HIP-graph step with the simplified model, a view cone turned every step, agent
+    classes and parked agents gives the same bits as direct launches."""
+    import math
+    from paper_2408_01584_amd import scenes as S
+    from paper_2408_01584_amd.sim import Sim
+    sc = S.make_scene(4, worlds=[1, 2, 3])
+    rng = np.random.default_rng(4)
+    sc.agent_class = rng.choice(np.array([0, 1, 2], np.uint8), sc.num_agents)
+    p = dataclasses.replace(sc.params, dynamics=1, lidar_fov=math.radians(100.0), min_goal_dist=40.0)
+    acts = torch.as_tensor(S.make_delta_actions(4, 5, sc.num_agents), device="cuda")
+    heads = torch.as_tensor(rng.uniform(-2, 2, (5, sc.num_agents)).astype(np.float32), device="cuda")
+    ref = Sim(sc, params=p)
+    gr = Sim(sc, params=p, graph=True)
+    for k in range(5):
+        for s in (ref, gr):
+            s.buf["lidar_head"][:sc.num_agents].copy_(heads[k])
+            s.step(acts[k])
+        a, b = ref.host_outputs(), gr.host_outputs()
+        for n in a:
+            assert np.array_equal(a[n], b[n]), (k, n)
+    assert (a["flags"] & 64).any() and (a["lidar_hit"] == 2).any()
