@@ -1,12 +1,14 @@
 // The batched step, fused into one kernel launch: one workgroup per world.
 //
-//   phase 1  bicycle dynamics of the alive agents (App. B)
-//   phase 2  agent/agent oriented-box collision (all pairs of the world, spread over the
-//            workgroup) and agent/road-edge collision (one wave per agent over the edge
-//            segments of the grid cells under the box) -- Sec. 3.1, Sec. 3.2
-//   phase 3  goal, reward, done, world done; auto-reset from the snapshot (Sec. 3.2
-//            "Rewards", "Termination")
-//   phase 4  ego observation (thread per agent)
+//   phase 1  dynamics of the alive agents: bicycle model (App. B) or the simplified model
+//            (Sec. 3.2 "Dynamics")
+//   phase 2  collisions of the alive agents, one wave per agent: against the other alive
+//            and the parked agents (oriented boxes) and, except for pedestrians, against
+//            the road-edge segments of the grid cells under the box -- Sec. 3.1, Sec. 3.2
+//   phase 3  goal, reward, done, world done; auto-reset from the snapshot, agents that
+//            start near their goal parked (Sec. 3.2 "Rewards", "Termination", "Sharp
+//            edges")
+//   phase 4  ego observation (thread per agent; parked agents observe nothing)
 //   phase 5  partner observation and road radius filter + top-K (wave per agent; Fig. 1,
 //            Sec. 3.2 "Sensor modalities")
 //
