@@ -542,13 +542,24 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
         sim->ctl.cell_cap4 = (max_cells + 1 + 3) / 4 * 4;
         sim->ctl.edge_cap = edge_cap;
         sim->ctl.cand_cap = cand_cap;
-        // LIDAR: the world's agents, and its edge segments when they fit, staged in LDS
+        // LIDAR: the world's agents staged in LDS, and its edge segments too when that
+        // keeps as many workgroups resident per compute unit as reading them through the
+        // caches (on 4096 worlds of 6000 points, staging left one workgroup per CU and
+        // took 0.54 ms per launch, reading through the caches 0.44 ms)
         sim->lctl.agent_cap = std::max(max_agents, 1);
         sim->lctl.cell_cap4 = sim->ctl.cell_cap4;
         sim->lctl.waves = kLidarMaxWaves;
-        sim->lctl.edge_cap = max_edges;
-        if (cfg->lidar_rays > 0 && lidar_lds_bytes(cfg->lidar_rays, sim->lctl) > (size_t)kLdsBytes)
-            sim->lctl.edge_cap = 0;
+        sim->lctl.edge_cap = 0;
+        if (cfg->lidar_rays > 0) {
+            const size_t glob = lidar_lds_bytes(cfg->lidar_rays, sim->lctl);
+            LidarCtl staged = sim->lctl;
+            staged.edge_cap = max_edges;
+            const size_t lds = lidar_lds_bytes(cfg->lidar_rays, staged);
+            const size_t wg_cap = (size_t)(kWave * 32) / ((size_t)kLidarMaxWaves * kWave);  // 32 waves per CU
+            auto resident = [&](size_t bytes) { return std::min(wg_cap, (size_t)kLdsBytes / std::max(bytes, (size_t)1)); };
+            if (max_edges > 0 && lds <= (size_t)kLdsBytes && resident(lds) >= resident(glob))
+                sim->lctl.edge_cap = max_edges;
+        }
         if (cfg->lidar_rays > 0 && lidar_lds_bytes(cfg->lidar_rays, sim->lctl) > (size_t)kLdsBytes) {
             delete sim;
             return fail(GD_E_SIZE, "LIDAR: %d rays and %d agents per world do not fit the LDS",

@@ -9,8 +9,9 @@
 // the head angle for a cone), in which the ray directions are the same for all agents.
 //
 // One workgroup per world.  The world's agents (position, heading, half extents, flags)
-// and, when they fit, its edge segments with their grid rows are staged in LDS first, so
-// the per-agent loop reads nothing from global memory.  Then one wave per agent, lanes
+// are staged in LDS first, and its edge segments with their grid rows too when that does
+// not cost resident workgroups (the host decides; otherwise they are read through the
+// caches).  Then one wave per agent, lanes
 // over the candidate segments: edge segments keyed in the grid rows that meet the disc of
 // radius range + longest segment, then the four sides of every other visible agent within
 // range.  Each candidate is moved into the ego frame; those whose closest point lies
