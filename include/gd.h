@@ -8,7 +8,7 @@
  *   - road map as polylines of typed points                     (Sec. 3.1, Sec. 3.2 "Dataset")
  *   - kinematic bicycle dynamics driven by (acceleration, steering)   (Sec. 3.2, App. B),
  *     or the simplified invertible model and its expert-action inversion
- *                                                            (Sec. 3.2 "Dynamics")
+ *                                                            (Sec. 3.2 "Agent dynamics")
  *   - collision of convex boxes with each other and with road edges
  *                                       (Sec. 3.1; Sec. 3.2 "Termination", "Sharp edges")
  *   - radius-filter observations in the agent's relative frame; planar LIDAR
@@ -95,7 +95,7 @@ typedef enum {
 
 /* gd_config.dynamics */
 #define GD_DYN_BICYCLE 0  /* kinematic bicycle model (App. B); actions (accel, steer rad) */
-#define GD_DYN_DELTA 1    /* simplified, invertible model (Sec. 3.2 "Dynamics"); actions
+#define GD_DYN_DELTA 1    /* simplified, invertible model (Sec. 3.2 "Agent dynamics"); actions
                              (accel, curvature command 1/m) */
 
 #define GD_MAX_AGENTS_PER_WORLD 1024
@@ -209,7 +209,7 @@ gd_status gd_reset(gd_sim *sim, const uint8_t *world_mask, void *stream);
  *      [A,2] = (accel m/s^2, steer rad): vbar = clip(v + a dt/2, +-v_max),
  *      beta = atan(tan(steer)/2), x += vbar cos(yaw + beta) dt,
  *      y += vbar sin(yaw + beta) dt, yaw += vbar cos(beta) tan(steer) / length dt,
- *      v = clip(v + a dt, +-v_max).  GD_DYN_DELTA (Sec. 3.2 "Dynamics"), actions
+ *      v = clip(v + a dt, +-v_max).  GD_DYN_DELTA (Sec. 3.2 "Agent dynamics"), actions
  *      (accel m/s^2, curvature command s 1/m): d = v dt + a dt^2/2, x += d cos(yaw),
  *      y += d sin(yaw), yaw += s d, v += a dt (no clip, independent of the length);
  *   2. collision flags of the alive agents, on the new state: against the other alive
@@ -269,7 +269,7 @@ gd_status gd_rollout_bwd(gd_sim *sim, const float *actions, const float *ckpt, i
                          int32_t ckpt_every, const float *grad_rewards, float *grad_actions,
                          float *grad_state0, void *stream);
 
-/* Expert-action inversion for the simplified model (Sec. 3.2 "Dynamics": the model is
+/* Expert-action inversion for the simplified model (Sec. 3.2 "Agent dynamics": the model is
  * invertible for unbounded actions, which makes logged trajectories usable as
  * demonstrations).  states [T+1,4,A] (x, y, yaw, speed per step, device, the layout of
  * the rollout checkpoints) -> actions [T,A,2] (device) with, for each step t,

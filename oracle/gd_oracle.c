@@ -9,8 +9,8 @@
  *   - kinematic bicycle model about the centre of gravity, l_r = L/2, midpoint speed
  *     clipped to +-v_max, explicit Euler                          (App. B, all equations)
  *   - the simplified, invertible bicycle model (a double integrator along the heading
- *     with the yaw update of Sec. 3.2 "Dynamics") and its inversion: the actions that
- *     carry one logged state to the next                          (Sec. 3.2 "Dynamics")
+ *     with the yaw update of Sec. 3.2 "Agent dynamics") and its inversion: the actions that
+ *     carry one logged state to the next                          (Sec. 3.2 "Agent dynamics")
  *   - agent/agent and agent/road-edge collision of convex boxes and edge segments
  *                                        (Sec. 3.1; Sec. 3.2 "Termination", "Sharp edges")
  *   - goal reached within a configurable distance, reward 1 (+ optional collision

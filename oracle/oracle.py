@@ -118,7 +118,7 @@ def dynamics(x, y, yaw, v, length, actions, dt=0.1, v_max=30.0, alive=None):
 
 
 def delta_dynamics(x, y, yaw, v, actions, dt=0.1, alive=None):
-    """One step of the simplified bicycle model (Sec. 3.2 "Dynamics") in FP64: actions are
+    """One step of the simplified bicycle model (Sec. 3.2 "Agent dynamics") in FP64: actions are
     (acceleration m/s^2, curvature command 1/m); returns new arrays."""
     x, y, yaw, v = (np.array(a, dtype=np.float64, copy=True) for a in (x, y, yaw, v))
     act = np.ascontiguousarray(actions, dtype=np.float64).reshape(-1, 2)

@@ -145,7 +145,7 @@ __device__ __forceinline__ float wrap_pi(float a) {
     return r;
 }
 
-// Simplified bicycle model (Sec. 3.2 "Dynamics"): a double integrator along the heading
+// Simplified bicycle model (Sec. 3.2 "Agent dynamics"): a double integrator along the heading
 // held during the step, the yaw turning by the command s (1/m) times the distance covered.
 // No clip, no dependence on the vehicle length.
 __device__ __forceinline__ void delta_model(float &x, float &y, float &yaw, float &v, float acc,

@@ -1,7 +1,7 @@
 // The batched step, fused into one kernel launch: one workgroup per world.
 //
 //   phase 1  dynamics of the alive agents: bicycle model (App. B) or the simplified model
-//            (Sec. 3.2 "Dynamics")
+//            (Sec. 3.2 "Agent dynamics")
 //   phase 2  collisions of the alive agents, one wave per agent: against the other alive
 //            and the parked agents (oriented boxes) and, except for pedestrians, against
 //            the road-edge segments of the grid cells under the box -- Sec. 3.1, Sec. 3.2
@@ -38,7 +38,7 @@ namespace gdk {
 
 // ---- dynamics.  Bicycle model (App. B): midpoint speed clipped to +-v_max, slip angle
 // beta = atan(tan(steer)/2) (l_r = L/2), explicit Euler.  The simplified model (Sec. 3.2
-// "Dynamics") is the same update with beta = 0, the command u as the curvature and no
+// "Agent dynamics") is the same update with beta = 0, the command u as the curvature and no
 // clip: with vb = v + a dt/2 the distance of the step is vb dt = v dt + a dt^2/2.  Both
 // go through one code path with selects, so that the step kernel carries one copy of it.
 __device__ __forceinline__ void move_agent(float &x, float &y, float &yaw, float &v, float L,

@@ -64,7 +64,7 @@ class SimParams:
     collision_penalty: float = 0.0
     auto_reset: bool = True
     terminate_on_collision: bool = False
-    dynamics: int = 0  # 0: bicycle model (App. B); 1: simplified model (Sec. 3.2 "Dynamics")
+    dynamics: int = 0  # 0: bicycle model (App. B); 1: simplified model (Sec. 3.2 "Agent dynamics")
     lidar_fov: float = 0.0  # 0: LIDAR rays around the full circle; > 0: view-cone width (rad)
     min_goal_dist: float = 0.0  # > 0: agents starting within it of their goal are parked
 

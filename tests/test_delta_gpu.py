@@ -1,4 +1,4 @@
-"""The simplified bicycle model (Sec. 3.2 "Dynamics") on the GPU against the FP64 oracle:
+"""The simplified bicycle model (Sec. 3.2 "Agent dynamics") on the GPU against the FP64 oracle:
 the full step teacher-forced, the differentiable rollout and its backward kernel, and the
 expert-action inversion element by element, plus a round trip of the inversion through
 the GPU's own rollout."""

@@ -1,4 +1,4 @@
-"""Pins of the oracle's simplified bicycle model (Sec. 3.2 "Dynamics": a double integrator
+"""Pins of the oracle's simplified bicycle model (Sec. 3.2 "Agent dynamics": a double integrator
 in position and speed along the heading, the yaw turning by the steering command times
 the distance covered) and of its inversion, against closed forms, a circle fit and
 round trips; its vector-Jacobian product against FP64 central finite differences."""
