@@ -139,3 +139,23 @@ def test_null_handles(G):
     assert L.gd_reset(None, None, None) == G.GD_E_ARG
     assert L.gd_check(None, None) == G.GD_E_ARG
     assert L.gd_rollout_fwd(None, None, 1, 1, None, None, None) == G.GD_E_ARG
+
+
+def test_decimate_argument_checks(G):
+    """Host-side validation of the decimation entry points (no device call is made)."""
+    assert G.gd_decimate_workspace_size(0) == 0
+    ws = G.gd_decimate_workspace_size(1000)
+    assert ws >= 12 * 1000 and ws % 256 == 0
+    with pytest.raises(G.GDError) as e:
+        G.gd_decimate_workspace_size(-1)
+    assert e.value.status == G.GD_E_ARG
+    fake = 1 << 20  # never dereferenced: every call below fails before any device work
+    cases = [((fake, -1, 10), 0.1, ws, G.GD_E_ARG), ((fake, 2, -5), 0.1, ws, G.GD_E_ARG),
+             ((fake, 2, 1000), float("nan"), ws, G.GD_E_ARG), ((fake, 2, 1000), -1.0, ws, G.GD_E_ARG),
+             ((fake, 2, 1000), 0.1, ws - 256, G.GD_E_SIZE), ((0, 2, 1000), 0.1, ws, G.GD_E_ARG)]
+    for (po, npoly, npts), area, wsb, status in cases:
+        with pytest.raises(G.GDError) as e:
+            G.gd_decimate(po, npoly, npts, fake, fake, area, fake, fake, fake, wsb, 0)
+        assert e.value.status == status, (npoly, npts, area, wsb)
+    # nothing to do: returns at once
+    G.gd_decimate(0, 0, 0, 0, 0, 0.1, 0, 0, 0, 0, 0)
