@@ -43,6 +43,8 @@ def parse():
                     help="replay a HIP graph per step instead of launching the kernel directly")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for HBM counter calibration)")
+    ap.add_argument("--cpu-baselines", action="store_true",
+                    help="time the oracle on bounded samples of every workload (host cores only)")
     ap.add_argument("--ingest", action="store_true",
                     help="time the road decimation of the headline workload's map sampled every "
                          "0.1 m, and the step on the decimated map")
@@ -119,6 +121,9 @@ def main():
         sys.exit(2)
     if args.ingest:
         ingest_leg(args)
+        return
+    if args.cpu_baselines:
+        print(json.dumps(cpu_baselines_all()), flush=True)
         return
     if args.config != 1:
         secondary(args)
@@ -478,6 +483,45 @@ def delta_model_legs(scene, T, c):
                        "algorithmic_bytes_per_launch": nbytes, "achieved_GBps": round(gbs, 1),
                        "hbm_frac": round(gbs * 1e9 / HBM_PEAK, 4),
                        "same_bytes_copy_GBps": round(nbytes / (ms_copy * 1e-3) / 1e9, 1)}}
+
+
+def cpu_baselines_all():
+    """The oracle (plain C, OpenMP over worlds) on bounded samples of every workload, on the
+    host's cores: the full step for configs 0, 2 (64 of its 1024 worlds) and 4 (32 of 4096
+    worlds, LIDAR included), and the differentiable rollout forward and vector-Jacobian
+    product for config 3 (all 512 worlds, T = 20)."""
+    import numpy as np
+
+    from oracle import oracle as O
+    from paper_2408_01584_amd import scenes as S
+    O.build(force=False)
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    out = {"kind": "oracle", "cores": cores, "unit": "agent-steps/s"}
+    for c, worlds, steps in ((0, None, 91), (2, 64, 20), (4, 32, 3)):
+        sc = S.make_scene(c, worlds=worlds) if worlds else S.make_scene(c)
+        acts = S.make_actions(c, steps + 1, sc.num_agents).astype(np.float64)
+        sim = O.OracleSim(sc)
+        sim.step(acts[0])
+        t = time.perf_counter()
+        for k in range(1, steps + 1):
+            sim.step(acts[k])
+        dt = time.perf_counter() - t
+        out["config_%d" % c] = {"value": round(sc.num_agents * steps / dt, 1),
+                                "sample": "%d worlds x %d steps, %.2f s" % (sc.num_worlds, steps, dt)}
+    sc = S.make_scene(3)
+    T = 20
+    acts = S.make_actions(3, T, sc.num_agents).astype(np.float64)
+    sim = O.OracleSim(sc)
+    t = time.perf_counter()
+    sim.rollout(acts)
+    dt_f = time.perf_counter() - t
+    t = time.perf_counter()
+    sim.rollout_vjp(acts, np.ones((T, sc.num_agents)))
+    dt_b = time.perf_counter() - t
+    out["config_3"] = {"rollout_fwd": round(sc.num_agents * T / dt_f, 1),
+                       "rollout_vjp": round(sc.num_agents * T / dt_b, 1),
+                       "sample": "512 worlds, T = 20, %.2f s + %.2f s" % (dt_f, dt_b)}
+    return out
 
 
 def cpu_baseline_decimation(dense, min_area):
