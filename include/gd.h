@@ -193,9 +193,9 @@ gd_status gd_workspace_size(const gd_config *cfg, const int32_t *h_agent_off,
  * against the host offsets, builds each world's uniform road grid and edge-segment grid
  * in the workspace (the broad phase that replaces the paper's BVH), snapshots the current
  * state as every world's initial state, and resets all worlds (flags ALIVE|VISIBLE, or
- * VISIBLE|STATIC for agents parked by min_goal_dist,
- * t = 0, observations computed).  Synchronises `stream` before returning.  On success
- * *out receives a handle to release with gd_destroy. */
+ * VISIBLE|STATIC for agents parked by min_goal_dist; t = 0; observations computed).
+ * Synchronises `stream` before returning.  On success *out receives a handle to release
+ * with gd_destroy. */
 gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off,
                     const int32_t *h_road_off, const gd_buffers *bufs, void *stream,
                     gd_sim **out);
