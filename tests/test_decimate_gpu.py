@@ -42,9 +42,10 @@ def test_dense_map_matches_oracle(gpu, oracle_mod, min_area):
 
 
 def test_long_polylines_use_the_workspace(gpu, oracle_mod):
-    """Polylines of 4097 and 9000 points (beyond the 4096 staged in LDS) beside short ones."""
+    """Polylines of 4097 and 9000 points (beyond the 4096 staged in LDS) beside short and
+    empty ones."""
     rng = np.random.default_rng(7)
-    lens = [4097, 5, 9000, 1, 2, 3, 4096, 64, 65]
+    lens = [4097, 5, 0, 9000, 1, 2, 3, 4096, 0, 64, 65]  # with empty polylines
     xs, ys = [], []
     for n in lens:
         s = np.arange(n) * 0.1

@@ -79,7 +79,7 @@ def _cone_run(sc, oracle_mod, fov, N, steps, seed, head_range=math.pi):
     return hits
 
 
-@pytest.mark.parametrize("fov_deg,N", [(120.0, 61), (360.0, 64), (0.6, 16)])
+@pytest.mark.parametrize("fov_deg,N", [(120.0, 61), (360.0, 64), (0.6, 16), (90.0, 1)])
 def test_view_cone_matches_oracle(gpu, oracle_mod, fov_deg, N):
     """View cones of 120 degrees (the paper's human view), the full turn, and a cone far
     narrower than the angle widening, on two worlds of the LIDAR workload, with the head
@@ -87,7 +87,7 @@ def test_view_cone_matches_oracle(gpu, oracle_mod, fov_deg, N):
     from paper_2408_01584_amd import scenes as S
     sc = S.make_scene(4, worlds=[0, 9])
     hits = _cone_run(sc, oracle_mod, math.radians(fov_deg), N, 3, seed=int(fov_deg * 10))
-    assert hits[1] > 0 and hits[2] > 0, hits
+    assert hits[1] > 0 and (hits[2] > 0 or N == 1), hits
     print("cone %.1f deg x %d rays: hit counts %s" % (fov_deg, N, hits.tolist()))
 
 
