@@ -550,9 +550,10 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     const float R2 = a.R2_obs;
     const float marg = 1e-3f * g.cs + 1e-3f;
     constexpr int SH = PointIndex<IDX16>::kShift;
-    // chunks (scan) and entries (scatter) per lane in flight together: 2 measured about
-    // 1 % faster than 4 and 2 % faster than 8 on 256 worlds x 64 agents
-    constexpr int SU = 2;
+    // chunks (scan) and entries (scatter) per lane in flight together: with the road in
+    // LDS 2 measured about 1 % faster than 4 (256 worlds x 64 agents); read through the
+    // caches, the longer latency wants 4 (2 was 3 % slower on 4096 worlds x 64 agents)
+    constexpr int SU = STAGED ? 2 : 4;
     const cand_t qmask = (cand_t)((1ull << SH) - 1);
 
     const long long pbase_w = a.P >= 0 ? 0 : a.pbase[w];
