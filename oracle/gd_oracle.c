@@ -28,12 +28,16 @@
  *     differentiable rollouts (an extension; the reward shape follows the configurable
  *     "agent-road distance" rewards of Sec. 3.2 "Rewards").
  *
- * Precision: everything is FP64, except the decisions that depend only on +,-,* of
- * positions (radius filters, goal test, the road-point ranking key).  Those are taken in
- * binary32 from binary32-rounded positions, with the operation order
+ * Precision: everything is FP64.  The decisions that depend only on +,-,* of positions
+ * (radius filters, goal test, the "all nontrivial" parking test, the road-point ranking
+ * key) compare the FP64 squared distance dx*dx + dy*dy with the squared threshold: the
+ * plain definition.  Decisions within 1e-4 m of a threshold, and near ties at the K-th
+ * road point, are marked in `band` for the comparisons to count and exclude.  A secondary
+ * mode (or_config.decide32 = 1) takes those decisions instead in binary32 from
+ * binary32-rounded positions with the operation order
  *     dx = fl(qx - px); dy = fl(qy - py); d2 = fl(fl(dx*dx) + fl(dy*dy))
- * which is the precision of the GPU kernels, so that the integer outcomes can be
- * compared bit for bit.  Build with -ffp-contract=off.
+ * so that an implementation with that arithmetic can also be compared bit for bit,
+ * including inside the band.  Build with -ffp-contract=off.
  *
  * Parity pins (tests/test_oracle_*.py): straight-line and constant-steer closed forms,
  * clip saturation, SAT against brute-force polygon intersection, top-K against a library
@@ -72,6 +76,8 @@ typedef struct {
     int32_t model; /* OR_MODEL_BICYCLE or OR_MODEL_DELTA */
     double lidar_fov; /* 0: rays around the full circle; (0, 2 pi]: view cone of this width */
     double min_goal_dist; /* > 0: agents starting within it of their goal are not controlled */
+    int32_t decide32;     /* 0: distance decisions in FP64 (the definition); 1: in binary32
+                             with the fixed operation order (secondary check) */
 } or_config;
 
 #define OR_MODEL_BICYCLE 0
@@ -107,9 +113,10 @@ typedef struct {
     int32_t *lidar_hit;   /* [A,N] */
     double *reward;       /* [A] */
     uint8_t *world_done;  /* [W] */
-    uint8_t *band;        /* [A] bit0 collision near touch, bit1 goal near threshold,
-                             bit2 partner radius near threshold, bit3 road K-th near tie,
-                             bit4 lidar near tie */
+    uint8_t *band;        /* [A] bit0 collision near touch, bit1 goal (or parking) near
+                             threshold, bit2 partner radius near threshold, bit3 road K-th
+                             near tie, bit4 lidar near tie, bit5 a road point near the
+                             radius that could be selected */
 } or_outputs;
 
 /* ------------------------------------------------------------------ helpers */
@@ -131,6 +138,24 @@ static float r2_32(double r) {
     volatile float rf = (float)r;
     volatile float r2 = rf * rf;
     return r2;
+}
+
+/* |q - p| <= r, decided in FP64 (the definition) or in binary32 (or_config.decide32) */
+static double key64(double px, double py, double qx, double qy) {
+    double dx = qx - px, dy = qy - py;
+    return dx * dx + dy * dy;
+}
+
+static int within(const or_config *c, double px, double py, double qx, double qy, double r) {
+    if (c->decide32) return key32((float)px, (float)py, (float)qx, (float)qy) <= r2_32(r);
+    return key64(px, py, qx, qy) <= r * r;
+}
+
+/* ranking key of a road point: FP64 squared distance, or the binary32 one (exactly
+   representable in a double, so the order is the binary32 order) */
+static double rank_key(const or_config *c, double px, double py, double qx, double qy) {
+    if (c->decide32) return (double)key32((float)px, (float)py, (float)qx, (float)qy);
+    return key64(px, py, qx, qy);
 }
 
 /* partner slots of agent with local index l in a world of n agents */
@@ -323,7 +348,7 @@ static void collide_world(const or_batch *b, int w, uint8_t *coll, uint8_t *band
 /* ------------------------------------------------------------------ observations */
 
 typedef struct {
-    float key;
+    double key;
     int32_t idx;
 } keyed;
 
@@ -375,7 +400,6 @@ static void obs_world(const or_batch *b, const or_config *c, int w, const or_out
     int a0 = b->agent_off[w], a1 = b->agent_off[w + 1], n = a1 - a0;
     int r0 = b->road_off[w], r1 = b->road_off[w + 1];
     int K = c->top_k, N = c->lidar_rays, P = num_slots(b, c, w);
-    float R2 = r2_32(c->obs_radius);
     double R = c->obs_radius;
     for (int i = a0; i < a1; i++) {
         int l = i - a0;
@@ -403,7 +427,6 @@ static void obs_world(const or_batch *b, const or_config *c, int w, const or_out
         if (!vis) continue;
         double px = b->x[i], py = b->y[i], th = b->yaw[i];
         double ct = cos(th), st = sin(th);
-        float pxf = (float)px, pyf = (float)py;
         /* ego: speed, length, width, goal in the ego frame, collision flags of the
            observed state (zero at episode start), valid */
         double gdx = b->gx[i] - px, gdy = b->gy[i] - py;
@@ -420,10 +443,9 @@ static void obs_world(const or_batch *b, const or_config *c, int w, const or_out
         for (int s = 0; s < P && s < n - 1; s++) {
             int j = a0 + (s < l ? s : s + 1);
             if (!(b->flags[j] & OR_VISIBLE)) continue;
-            float d2 = key32(pxf, pyf, (float)b->x[j], (float)b->y[j]);
-            double d64 = sqrt((b->x[j] - px) * (b->x[j] - px) + (b->y[j] - py) * (b->y[j] - py));
+            double d64 = sqrt(key64(px, py, b->x[j], b->y[j]));
             if (o->band && fabs(d64 - R) < OR_BAND) o->band[i] |= 4;
-            if (!(d2 <= R2)) continue;
+            if (!within(c, px, py, b->x[j], b->y[j], R)) continue;
             double dx = b->x[j] - px, dy = b->y[j] - py;
             double *f = o->partner + (sb + s) * 6;
             f[0] = ct * dx + st * dy;
@@ -435,16 +457,25 @@ static void obs_world(const or_batch *b, const or_config *c, int w, const or_out
             o->pmask[sb + s] = 1;
         }
         /* road: radius filter, then the K smallest (d2, index) in ascending order */
-        int cnt = 0;
+        int cnt = 0, near_r = 0;
         for (int k = r0; k < r1; k++) {
-            float d2 = key32(pxf, pyf, (float)b->rx[k], (float)b->ry[k]);
-            if (d2 <= R2) {
-                scratch[cnt].key = d2;
+            if (fabs(sqrt(key64(px, py, b->rx[k], b->ry[k])) - R) < OR_BAND) near_r = 1;
+            if (within(c, px, py, b->rx[k], b->ry[k], R)) {
+                scratch[cnt].key = rank_key(c, px, py, b->rx[k], b->ry[k]);
                 scratch[cnt].idx = k - r0;
                 cnt++;
             }
         }
         qsort(scratch, (size_t)cnt, sizeof(keyed), cmp_keyed);
+        /* a point within 1e-4 m of the radius changes the selection when the K-th point
+           (or the end of a short list) lies within 1e-4 m of the radius too */
+        if (o->band && near_r && K > 0) {
+            if (cnt <= K) o->band[i] |= 32;
+            else {
+                int kk = r0 + scratch[K - 1].idx;
+                if (hypot(b->rx[kk] - px, b->ry[kk] - py) > R - OR_BAND) o->band[i] |= 32;
+            }
+        }
         int take = cnt < K ? cnt : K;
         for (int q = 0; q < take; q++) {
             int k = r0 + scratch[q].idx;
@@ -473,7 +504,10 @@ static void obs_world(const or_batch *b, const or_config *c, int w, const or_out
             double ang = cone ? th + head + c->lidar_fov * (((double)k + 0.5) / (double)N - 0.5)
                               : th + 2.0 * OR_PI * (double)k / (double)N;
             double dx = cos(ang), dy = sin(ang);
+            /* hits are searched up to range + band: a hit within the band of the range
+               (in or out of it) is an ambiguous decision */
             double best = c->lidar_range, second = INFINITY;
+            double text = c->lidar_range + OR_BAND;
             int hit = 0;
             int graze = 0;
             for (int e = r0; e < r1 - 1; e++) {
@@ -481,7 +515,9 @@ static void obs_world(const or_batch *b, const or_config *c, int w, const or_out
                 graze |= ray_segment_grazes(px, py, dx, dy, b->rx[e], b->ry[e], b->rx[e + 1],
                                             b->ry[e + 1], c->lidar_range);
                 double tt = or_ray_segment(px, py, dx, dy, b->rx[e], b->ry[e], b->rx[e + 1],
-                                           b->ry[e + 1], c->lidar_range);
+                                           b->ry[e + 1], text);
+                if (tt > c->lidar_range - OR_BAND) graze = 1;
+                if (tt > c->lidar_range) continue;
                 if (tt > 0.0) {
                     if (tt < best) { second = best; best = tt; hit = 1; }
                     else if (tt < second) second = tt;
@@ -496,8 +532,9 @@ static void obs_world(const or_batch *b, const or_config *c, int w, const or_out
                                                 cr[(q + 1) % 4][0], cr[(q + 1) % 4][1],
                                                 c->lidar_range);
                     double tt = or_ray_segment(px, py, dx, dy, cr[q][0], cr[q][1],
-                                               cr[(q + 1) % 4][0], cr[(q + 1) % 4][1],
-                                               c->lidar_range);
+                                               cr[(q + 1) % 4][0], cr[(q + 1) % 4][1], text);
+                    if (tt > c->lidar_range - OR_BAND) graze = 1;
+                    if (tt > c->lidar_range) continue;
                     if (tt > 0.0) {
                         if (tt < best) { second = best; best = tt; hit = 2; }
                         else if (tt < second) second = tt;
@@ -506,8 +543,7 @@ static void obs_world(const or_batch *b, const or_config *c, int w, const or_out
             }
             o->lidar[(int64_t)i * N + k] = best;
             o->lidar_hit[(int64_t)i * N + k] = hit;
-            if (o->band && (second - best < OR_BAND || fabs(best - c->lidar_range) < OR_BAND || graze))
-                o->band[i] |= 16;
+            if (o->band && (second - best < OR_BAND || graze)) o->band[i] |= 16;
         }
     }
 }
@@ -548,10 +584,10 @@ void or_collide(const or_batch *b, uint8_t *coll_out, uint8_t *band) {
    its goal (binary32 key, inclusive; band bit 2 within 1e-4 m of the threshold). */
 static uint8_t start_flags(const or_batch *b, const or_config *c, int i, uint8_t *band) {
     if (c->min_goal_dist > 0.0) {
-        float d2 = key32((float)b->x[i], (float)b->y[i], (float)b->gx[i], (float)b->gy[i]);
         double d = hypot(b->gx[i] - b->x[i], b->gy[i] - b->y[i]);
         if (band && fabs(d - c->min_goal_dist) < OR_BAND) band[i] |= 2;
-        if (d2 <= r2_32(c->min_goal_dist)) return OR_VISIBLE | OR_STATIC;
+        if (within(c, b->x[i], b->y[i], b->gx[i], b->gy[i], c->min_goal_dist))
+            return OR_VISIBLE | OR_STATIC;
     }
     return OR_ALIVE | OR_VISIBLE;
 }
@@ -592,7 +628,6 @@ static void step_world(const or_batch *b, const or_config *c, int w, const doubl
     /* 2-3. agent/agent and agent/edge collision on the post-dynamics state */
     collide_world(b, w, coll, o->band);
     /* 4. goal, reward, done */
-    float G2 = r2_32(c->goal_radius);
     int last = b->t[w] + 1 >= c->episode_len;
     int any_alive = 0;
     for (int i = a0; i < a1; i++) {
@@ -603,10 +638,9 @@ static void step_world(const or_batch *b, const or_config *c, int w, const doubl
         int done = 1;
         if (alive) {
             out |= coll[i - a0];
-            float d2 = key32((float)b->x[i], (float)b->y[i], (float)b->gx[i], (float)b->gy[i]);
             double d64 = hypot(b->gx[i] - b->x[i], b->gy[i] - b->y[i]);
             if (o->band && fabs(d64 - c->goal_radius) < OR_BAND) o->band[i] |= 2;
-            int goal = d2 <= G2;
+            int goal = within(c, b->x[i], b->y[i], b->gx[i], b->gy[i], c->goal_radius);
             int collided = (out & (OR_COLL_AGENT | OR_COLL_EDGE)) != 0;
             if (goal) out |= OR_GOAL;
             r = (goal ? 1.0 : 0.0) - (collided ? c->collision_penalty : 0.0);

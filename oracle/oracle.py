@@ -17,7 +17,9 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "gd_oracle.c")
-LIB = os.path.join(HERE, "liboracle.so")
+# GD_ORACLE_LIB points the loader at another build of the same source (the mutation
+# check of the oracle's pins builds planted-mistake copies there)
+LIB = os.environ.get("GD_ORACLE_LIB", os.path.join(HERE, "liboracle.so"))
 
 COLL_AGENT, COLL_EDGE, GOAL, DONE, ALIVE, VISIBLE, STATIC = 1, 2, 4, 8, 16, 32, 64
 VEHICLE, CYCLIST, PEDESTRIAN = 0, 1, 2
@@ -27,6 +29,8 @@ INV_MIN_DIST = 1e-3  # the inversion's distance threshold (m), as in gd_oracle.c
 
 
 def build(force: bool = True) -> str:
+    if "GD_ORACLE_LIB" in os.environ and os.path.exists(LIB):
+        return LIB  # a prebuilt copy chosen by the caller
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
@@ -53,7 +57,8 @@ class Config(C.Structure):
                 ("lidar_rays", C.c_int32), ("flags", C.c_uint32), ("dt", C.c_double),
                 ("obs_radius", C.c_double), ("goal_radius", C.c_double), ("v_max", C.c_double),
                 ("lidar_range", C.c_double), ("collision_penalty", C.c_double),
-                ("model", C.c_int32), ("lidar_fov", C.c_double), ("min_goal_dist", C.c_double)]
+                ("model", C.c_int32), ("lidar_fov", C.c_double), ("min_goal_dist", C.c_double),
+                ("decide32", C.c_int32)]
 
 
 class Batch(C.Structure):
@@ -92,12 +97,14 @@ def _p(a):
     return None if a is None else a.ctypes.data
 
 
-def config_from_params(p) -> Config:
+def config_from_params(p, decide32: bool = False) -> Config:
+    """decide32: take the distance decisions (radius filters, goal and parking tests, road
+    ranking key) in binary32 with the fixed operation order instead of FP64."""
     flags = (AUTO_RESET if p.auto_reset else 0) | (TERM_ON_COLLISION if p.terminate_on_collision else 0)
     return Config(p.top_k, p.partners, p.episode_len, p.lidar_rays, flags, p.dt, p.obs_radius,
                   p.goal_radius, p.v_max, p.lidar_range, p.collision_penalty,
                   getattr(p, "dynamics", MODEL_BICYCLE), getattr(p, "lidar_fov", 0.0),
-                  getattr(p, "min_goal_dist", 0.0))
+                  getattr(p, "min_goal_dist", 0.0), 1 if decide32 else 0)
 
 
 def partner_slots(agent_off: np.ndarray, partners: int) -> int:
@@ -168,12 +175,19 @@ def ray_segment(ox, oy, dx, dy, x0, y0, x1, y1, tmax) -> float:
 
 # --------------------------------------------------------------------------- simulator
 
-class OracleSim:
-    """FP64 simulator over a CSR-batched scene.  State and outputs are numpy arrays."""
+# band bits (per agent) of the oracle's outputs: a decision within 1e-4 m of its threshold
+BAND_COLL, BAND_GOAL, BAND_PARTNER_R, BAND_KTH, BAND_LIDAR, BAND_ROAD_R = 1, 2, 4, 8, 16, 32
 
-    def __init__(self, scene, params=None):
+
+class OracleSim:
+    """FP64 simulator over a CSR-batched scene.  State and outputs are numpy arrays.
+
+    decide32=True switches the distance decisions to the binary32 emulation (secondary
+    check); the default takes them in FP64, the plain definition."""
+
+    def __init__(self, scene, params=None, decide32=False):
         self.params = params if params is not None else scene.params
-        self.cfg = config_from_params(self.params)
+        self.cfg = config_from_params(self.params, decide32)
         self.agent_off = np.ascontiguousarray(scene.agent_off, dtype=np.int32)
         self.road_off = np.ascontiguousarray(scene.road_off, dtype=np.int32)
         f64 = lambda a: np.ascontiguousarray(a, dtype=np.float64).copy()
@@ -235,6 +249,10 @@ class OracleSim:
         r["flags"] = self.flags.copy()
         r["t"] = self.t.copy()
         r["state"] = np.stack([self.x, self.y, self.yaw, self.v]).copy()
+        # the scene geometry (shared, not copied), for comparisons that need FP64
+        # distances of points the oracle did not select
+        r["geom"] = dict(agent_off=self.agent_off, road_off=self.road_off, road_x=self.rx,
+                         road_y=self.ry, partners=self.params.partners)
         return r
 
     # -- state access (teacher forcing) --

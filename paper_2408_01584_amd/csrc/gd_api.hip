@@ -232,7 +232,8 @@ static bool launch_shape(const gd_config *c, int max_road, int max_cells, int ma
                          int max_agents, int &waves, int &bins, int &road_cap, int &edge_cap,
                          int &cand_cap, int &idx16) {
     idx16 = max_road < 65536 ? 1 : 0;
-    const int agent_cap = std::max(max_agents, 1);
+    // a multiple of 4 agents keeps the LDS regions after the agent arrays 16-byte aligned
+    const int agent_cap = (std::max(max_agents, 1) + 3) / 4 * 4;
     const int cell_cap4 = (max_cells + 1 + 3) / 4 * 4;
     const bool can_stage = c->top_k > 0 && idx16 && max_road <= 60000;
     Shape glob, lds;
@@ -483,7 +484,7 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
     a.pbase = (long long *)(ws + L.pbase);
     a.err = (unsigned *)(ws + L.err);
     sim->ctl.order = (const int *)(ws + L.order);
-    sim->ctl.agent_cap = std::max(max_agents, 1);
+    sim->ctl.agent_cap = (std::max(max_agents, 1) + 3) / 4 * 4;  // as in launch_shape
 
     std::vector<long long> pb(W);
     long long acc = 0;

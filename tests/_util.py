@@ -46,3 +46,10 @@ def key32(px, py, qx, qy):
     dx = (np.asarray(qx, np.float32) - px).astype(np.float32)
     dy = (np.asarray(qy, np.float32) - py).astype(np.float32)
     return (dx * dx).astype(np.float32) + (dy * dy).astype(np.float32)
+
+
+def key64(px, py, qx, qy):
+    """FP64 squared distance (the definition the oracle's decisions use by default)."""
+    dx = np.asarray(qx, np.float64) - np.float64(px)
+    dy = np.asarray(qy, np.float64) - np.float64(py)
+    return dx * dx + dy * dy

@@ -84,8 +84,10 @@ def _log(oracle_mod, A, T, seed, wrap=False):
 
 
 def _check_inversion(g, o, band):
+    # no step of these logs sits at a decision threshold of the inversion, so nothing is
+    # excluded (a change that put steps there would show here first)
     ok = band == 0
-    assert ok.mean() > 0.99
+    assert ok.all(), int((~ok).sum())
     assert_close(g[..., 0][ok], o[..., 0][ok], "accel")
     assert_close(g[..., 1][ok], o[..., 1][ok], "curvature")
 

@@ -151,3 +151,22 @@ def test_polyline_boundary_is_not_a_segment(oracle_mod):
     sc = _tiny_world(agents, [[(-10, -5), (-1, -5), (1, 5), (10, 5)]])
     coll, _ = oracle_mod.OracleSim(sc).collide()
     assert coll[0] == 2
+
+
+def test_near_touch_just_outside_the_band(oracle_mod):
+    """Boxes 0.5 mm apart do not collide and boxes overlapping by 0.5 mm do (strict
+    overlap, Sec. 3.2 "Termination"); both are outside the 1e-4 m band, so no band bit is
+    set.  The same for a road edge 0.5 mm beside a box and one 0.5 mm inside it."""
+    for gap, want in ((5e-4, 0), (-5e-4, 1)):
+        sc = _tiny_world([(0, 0, 0, 4.5, 2), (4.5 + gap, 0, 0, 4.5, 2)], [])
+        coll, band = oracle_mod.OracleSim(sc).collide()
+        assert list(coll) == [want, want], gap
+        assert not band.any(), gap
+    for gap, want in ((5e-4, 0), (-5e-4, 2)):
+        sc = _tiny_world([(0, 0, 0, 4.5, 2)], [[(-10, 1 + gap), (10, 1 + gap)]])
+        coll, band = oracle_mod.OracleSim(sc).collide()
+        assert coll[0] == want and not band.any(), gap
+    # within the band the decision is marked
+    sc = _tiny_world([(0, 0, 0, 4.5, 2), (4.5 + 5e-5, 0, 0, 4.5, 2)], [])
+    _, band = oracle_mod.OracleSim(sc).collide()
+    assert np.all(band & 1)

@@ -103,3 +103,39 @@ def test_offroad_sign_convention(oracle_mod):
     r_off = oracle_mod.OracleSim(off).rollout(z)["rewards"][0, 0]
     np.testing.assert_allclose(r_on, -math.log1p(math.exp(-3.0)), rtol=1e-12)
     np.testing.assert_allclose(r_off, -(3.0 + math.log1p(math.exp(-3.0))), rtol=1e-12)
+
+
+def test_smooth_reward_ignores_edges_beyond_the_radius(oracle_mod):
+    """With the only road edge just outside the observation radius the off-road term is
+    the constant softplus(-R).  A small radius (3 m) makes the difference visible: the
+    agent sits 3.5 m on the off-road side of the edge, where an edge inside the radius
+    would give softplus(+3.5)."""
+    from tests._util import tiny_world
+    from paper_2408_01584_amd import scenes as S
+    p = S.SimParams(top_k=4, partners=0, obs_radius=3.0)
+    edge = [[(-100.0, 0.0), (100.0, 0.0)]]  # runs +x: the drivable side is +y
+    goal = (0.0, -3.5)
+    out = tiny_world([(0.0, -3.5, 0.0, 4.5, 2.0)], goals=[goal], edges=edge, params=p)
+    r = oracle_mod.OracleSim(out).rollout(np.zeros((1, 1, 2)))
+    assert r["seg"][0, 0] == -1
+    np.testing.assert_allclose(r["rewards"][0, 0], -math.log1p(math.exp(-3.0)), rtol=1e-12)
+    # 2.5 m away the edge is inside the radius and the agent is off-road: s = +2.5
+    inside = tiny_world([(0.0, -2.5, 0.0, 4.5, 2.0)], goals=[(0.0, -2.5)], edges=edge, params=p)
+    r = oracle_mod.OracleSim(inside).rollout(np.zeros((1, 1, 2)))
+    assert r["seg"][0, 0] == 0
+    np.testing.assert_allclose(r["rewards"][0, 0], -(2.5 + math.log1p(math.exp(-2.5))), rtol=1e-12)
+
+
+def test_nearest_edge_ties_take_the_lowest_index(oracle_mod):
+    """Two edge segments at exactly the same distance, one with the agent on its off-road
+    side and one with it on its drivable side: the lower road index decides the sign of
+    the off-road distance (r = -softplus(+1) or -softplus(-1))."""
+    from tests._util import tiny_world
+    above = [(-10.0, 1.0), (10.0, 1.0)]    # agent on its right: off-road, s = +1
+    below = [(-10.0, -1.0), (10.0, -1.0)]  # agent on its left: on-road, s = -1
+    for edges, want_seg, s in (([above, below], 0, 1.0), ([below, above], 0, -1.0)):
+        sc = tiny_world([(0.0, 0.0, 0.0, 4.5, 2.0)], goals=[(0.0, 0.0)], edges=edges)
+        r = oracle_mod.OracleSim(sc).rollout(np.zeros((1, 1, 2)))
+        assert r["seg"][0, 0] == want_seg
+        softplus = max(s, 0.0) + math.log1p(math.exp(-abs(s)))
+        np.testing.assert_allclose(r["rewards"][0, 0], -softplus, rtol=1e-12)

@@ -1,7 +1,8 @@
 """Pins of the oracle's observations (Fig. 1: relative coordinate frame, 50 m radius;
 Sec. 3.2 "Sensor modalities": radius filter and LIDAR).
 
-Road top-K is compared with a library stable sort (numpy lexsort) of the binary32 key;
+Road top-K is compared with a library stable sort (numpy lexsort) of the FP64 key (and, in
+the oracle's secondary mode, of the binary32 key);
 ego-frame features with a complex-number rotation; invariance under rigid motions and
 permutations; LIDAR against closed-form wall and box distances.
 """
@@ -10,7 +11,7 @@ import math
 import numpy as np
 import pytest
 
-from tests._util import key32, tiny_world, wrap
+from tests._util import key32, key64, tiny_world, wrap
 
 
 @pytest.fixture(scope="module")
@@ -19,16 +20,20 @@ def cfg1_two_worlds():
     return S.make_scene(1, worlds=[0, 5])
 
 
-def test_road_topk_matches_library_sort(oracle_mod, cfg1_two_worlds):
+@pytest.mark.parametrize("decide32", [False, True])
+def test_road_topk_matches_library_sort(oracle_mod, cfg1_two_worlds, decide32):
     sc = cfg1_two_worlds
-    sim = oracle_mod.OracleSim(sc)
+    sim = oracle_mod.OracleSim(sc, decide32=decide32)
     r = sim.reset()
     K = sc.params.top_k
-    R2 = np.float32(np.float32(50.0) * np.float32(50.0))
+    if decide32:
+        R2, key = np.float32(np.float32(50.0) * np.float32(50.0)), key32
+    else:
+        R2, key = 2500.0, key64
     for w in range(sc.num_worlds):
         r0, r1 = sc.road_off[w], sc.road_off[w + 1]
         for i in range(sc.agent_off[w], sc.agent_off[w + 1]):
-            k = key32(sc.x[i], sc.y[i], sc.road_x[r0:r1], sc.road_y[r0:r1])
+            k = key(sc.x[i], sc.y[i], sc.road_x[r0:r1], sc.road_y[r0:r1])
             cand = np.nonzero(k <= R2)[0]
             order = cand[np.lexsort((cand, k[cand]))][:K]
             got = r["road_idx"][i]
@@ -64,7 +69,7 @@ def _rigid(sc, phi, tx, ty):
 
 def test_rigid_motion_invariance(oracle_mod, cfg1_two_worlds):
     """Ego-frame features do not change when the whole world is rotated and
-    translated; selected sets only change at near ties of the binary32 key."""
+    translated; selected sets only change at near ties of the key."""
     sc = cfg1_two_worlds
     base = oracle_mod.OracleSim(sc).reset()
     moved = oracle_mod.OracleSim(_rigid(sc, 0.83, 17.0, -9.0)).reset()
@@ -112,10 +117,10 @@ def test_road_permutation(oracle_mod):
         b = got["road_idx"][i]
         assert (a >= 0).sum() == (b >= 0).sum()
         n = (a >= 0).sum()
-        ka = key32(sc.x[i], sc.y[i], sc.road_x[a[:n]], sc.road_y[a[:n]])
-        kb = key32(sc.x[i], sc.y[i], sc.road_x[perm[b[:n]]], sc.road_y[perm[b[:n]]])
+        ka = key64(sc.x[i], sc.y[i], sc.road_x[a[:n]], sc.road_y[a[:n]])
+        kb = key64(sc.x[i], sc.y[i], sc.road_x[perm[b[:n]]], sc.road_y[perm[b[:n]]])
         np.testing.assert_array_equal(ka, kb)
-        if n < sc.params.top_k or ka[-1] != key32(sc.x[i], sc.y[i], sc.road_x, sc.road_y)[
+        if n < sc.params.top_k or ka[-1] != key64(sc.x[i], sc.y[i], sc.road_x, sc.road_y)[
                 np.setdiff1d(np.arange(sc.num_road), a[:n])].min():
             assert set(a[:n]) == set(perm[b[:n]])
 

@@ -124,3 +124,28 @@ def test_reset_mask(oracle_mod):
     np.testing.assert_array_equal(r["state"][:, a0:a1], fresh["state"][:, a0:a1])
     assert not np.array_equal(r["state"][:, :a0], fresh["state"][:, :a0])
     assert list(r["t"]) == [3, 0, 3]
+
+
+def test_fresh_episode_reports_no_collision(oracle_mod):
+    """A collision that ends the episode (terminate-on-collision, both agents done, the
+    world resets in the same step) is reported in the step's flags, but the returned
+    observation is the new episode's first, whose ego collision entries are 0: a fresh
+    episode has had no transition yet."""
+    O = oracle_mod
+    sc = tiny_world([(0.0, 0.0, 0.0, 4.5, 2.0), (3.0, 0.0, 0.0, 4.5, 2.0)],
+                    params=_params(terminate_on_collision=True, collision_penalty=0.5, partners=1))
+    sim = O.OracleSim(sc)
+    fresh = sim.reset()
+    r = sim.step(np.zeros((2, 2)))
+    assert r["world_done"][0] == 1 and r["t"][0] == 0
+    assert list(r["flags"] & (O.COLL_AGENT | O.DONE)) == [O.COLL_AGENT | O.DONE] * 2
+    np.testing.assert_allclose(r["reward"], [-0.5, -0.5])
+    assert np.all(r["ego"][:, 5:7] == 0.0)
+    np.testing.assert_array_equal(r["ego"], fresh["ego"])
+    # one step later (t = 1) the same overlap is reported in the observation
+    r = sim.step(np.zeros((2, 2)))
+    assert r["t"][0] == 0 and r["world_done"][0] == 1
+    sc2 = tiny_world([(0.0, 0.0, 0.0, 4.5, 2.0), (3.0, 0.0, 0.0, 4.5, 2.0)],
+                     params=_params(collision_penalty=0.5, partners=1))
+    r2 = O.OracleSim(sc2).step(np.zeros((2, 2)))
+    assert r2["t"][0] == 1 and np.all(r2["ego"][:, 5] == 1.0)
