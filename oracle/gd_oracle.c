@@ -372,8 +372,8 @@ double or_ray_segment(double ox, double oy, double dx, double dy, double x0, dou
     return -1.0;
 }
 
-/* 1 when the ray passes within OR_BAND of an end of the segment inside the range, or
-   runs along it: a hit that a perturbation of that size can create or remove */
+/* 1 when the ray passes within OR_BAND of an end of the segment that lies at most tmax
+   (+ OR_BAND) along it: a hit that a perturbation of that size can create or remove */
 static int ray_segment_grazes(double ox, double oy, double dx, double dy, double x0, double y0,
                               double x1, double y1, double tmax) {
     double ends[2][2] = {{x0, y0}, {x1, y1}};
@@ -512,8 +512,6 @@ static void obs_world(const or_batch *b, const or_config *c, int w, const or_out
             int graze = 0;
             for (int e = r0; e < r1 - 1; e++) {
                 if (!is_edge_segment(b->rmeta, e)) continue;
-                graze |= ray_segment_grazes(px, py, dx, dy, b->rx[e], b->ry[e], b->rx[e + 1],
-                                            b->ry[e + 1], c->lidar_range);
                 double tt = or_ray_segment(px, py, dx, dy, b->rx[e], b->ry[e], b->rx[e + 1],
                                            b->ry[e + 1], text);
                 if (tt > c->lidar_range - OR_BAND) graze = 1;
@@ -528,9 +526,6 @@ static void obs_world(const or_batch *b, const or_config *c, int w, const or_out
                 double cr[4][2];
                 box_corners(b->x[j], b->y[j], b->yaw[j], b->len[j], b->wid[j], cr);
                 for (int q = 0; q < 4; q++) {
-                    graze |= ray_segment_grazes(px, py, dx, dy, cr[q][0], cr[q][1],
-                                                cr[(q + 1) % 4][0], cr[(q + 1) % 4][1],
-                                                c->lidar_range);
                     double tt = or_ray_segment(px, py, dx, dy, cr[q][0], cr[q][1],
                                                cr[(q + 1) % 4][0], cr[(q + 1) % 4][1], text);
                     if (tt > c->lidar_range - OR_BAND) graze = 1;
@@ -539,6 +534,23 @@ static void obs_world(const or_batch *b, const or_config *c, int w, const or_out
                         if (tt < best) { second = best; best = tt; hit = 2; }
                         else if (tt < second) second = tt;
                     }
+                }
+            }
+            /* a ray passing within the band of a segment end at or before the nearest hit
+               decides that segment's hit at its threshold (s = 0 or 1), which can move the
+               nearest hit; ends beyond the nearest hit cannot change it */
+            if (o->band && !graze) {
+                for (int e = r0; e < r1 - 1 && !graze; e++)
+                    if (is_edge_segment(b->rmeta, e))
+                        graze |= ray_segment_grazes(px, py, dx, dy, b->rx[e], b->ry[e],
+                                                    b->rx[e + 1], b->ry[e + 1], best);
+                for (int j = a0; j < a1 && !graze; j++) {
+                    if (j == i || !(b->flags[j] & OR_VISIBLE)) continue;
+                    double cr[4][2];
+                    box_corners(b->x[j], b->y[j], b->yaw[j], b->len[j], b->wid[j], cr);
+                    for (int q = 0; q < 4; q++)
+                        graze |= ray_segment_grazes(px, py, dx, dy, cr[q][0], cr[q][1],
+                                                    cr[(q + 1) % 4][0], cr[(q + 1) % 4][1], best);
                 }
             }
             o->lidar[(int64_t)i * N + k] = best;
