@@ -117,6 +117,8 @@ typedef struct {
                              threshold, bit2 partner radius near threshold, bit3 road K-th
                              near tie, bit4 lidar near tie, bit5 a road point near the
                              radius that could be selected */
+    uint8_t *lidar_band;  /* [A,N] or NULL: 1 for each ray whose nearest hit is within
+                             1e-4 m of a threshold (band bit 4 is their union) */
 } or_outputs;
 
 /* ------------------------------------------------------------------ helpers */
@@ -422,6 +424,7 @@ static void obs_world(const or_batch *b, const or_config *c, int w, const or_out
             for (int k = 0; k < N; k++) {
                 o->lidar[(int64_t)i * N + k] = 0.0;
                 o->lidar_hit[(int64_t)i * N + k] = 0;
+                if (o->lidar_band) o->lidar_band[(int64_t)i * N + k] = 0;
             }
         }
         if (!vis) continue;
@@ -555,7 +558,10 @@ static void obs_world(const or_batch *b, const or_config *c, int w, const or_out
             }
             o->lidar[(int64_t)i * N + k] = best;
             o->lidar_hit[(int64_t)i * N + k] = hit;
-            if (o->band && (second - best < OR_BAND || graze)) o->band[i] |= 16;
+            if (o->band && (second - best < OR_BAND || graze)) {
+                o->band[i] |= 16;
+                if (o->lidar_band) o->lidar_band[(int64_t)i * N + k] = 1;
+            }
         }
     }
 }

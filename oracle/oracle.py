@@ -70,7 +70,8 @@ class Batch(C.Structure):
 
 class Outputs(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("ego", "partner", "pmask", "road", "road_idx", "lidar",
-                                         "lidar_hit", "reward", "world_done", "band")]
+                                         "lidar_hit", "reward", "world_done", "band",
+                                         "lidar_band")]
 
 
 def _declare(L):
@@ -217,7 +218,8 @@ class OracleSim:
                         pmask=np.zeros(S, np.uint8), road=np.zeros((A, K, 4)),
                         road_idx=np.zeros((A, K), np.int32), lidar=np.zeros((A, max(N, 1))),
                         lidar_hit=np.zeros((A, max(N, 1)), np.int32), reward=np.zeros(A),
-                        world_done=np.zeros(self.W, np.uint8), band=np.zeros(A, np.uint8))
+                        world_done=np.zeros(self.W, np.uint8), band=np.zeros(A, np.uint8),
+                        lidar_band=np.zeros((A, max(N, 1)), np.uint8))
 
     def _batch(self):
         b = Batch()
@@ -236,7 +238,7 @@ class OracleSim:
     def _outputs(self):
         o = Outputs()
         for k in ("ego", "partner", "pmask", "road", "road_idx", "lidar", "lidar_hit", "reward",
-                  "world_done", "band"):
+                  "world_done", "band", "lidar_band"):
             setattr(o, k, _p(self.out[k]))
         self._keep_o = o
         return o
@@ -246,6 +248,7 @@ class OracleSim:
         if self.N == 0:
             r["lidar"] = r["lidar"][:, :0]
             r["lidar_hit"] = r["lidar_hit"][:, :0]
+            r["lidar_band"] = r["lidar_band"][:, :0]
         r["flags"] = self.flags.copy()
         r["t"] = self.t.copy()
         r["state"] = np.stack([self.x, self.y, self.yaw, self.v]).copy()
