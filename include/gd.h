@@ -304,6 +304,21 @@ gd_status gd_decimate(const int32_t *poly_off, int32_t n_poly, int32_t n_points,
                       const float *y, float min_area, uint8_t *keep, float *dir, void *workspace,
                       size_t workspace_bytes, void *stream);
 
+/* Allocation-free variant of gd_decimate, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernel and the same results as gd_decimate, with the workspace
+ * taken from a device array of the library (one per GPU, held until the process ends)
+ * instead of a caller buffer.  Arguments, layouts and outputs as in gd_decimate;
+ * n_points must not exceed GD_DECIMATE_NOALLOC_MAX_POINTS (GD_E_SIZE otherwise, checked
+ * before anything is enqueued).  `stream` must belong to the current device.  Calls on
+ * one GPU share its array: calls that overlap in time on one GPU (different streams or
+ * host threads without ordering) race and give undefined results; calls ordered on one
+ * stream are safe.  No memory is allocated and nothing is freed. */
+#define GD_DECIMATE_NOALLOC_MAX_POINTS (1 << 22)
+gd_status gd_decimate_noalloc(const int32_t *poly_off, int32_t n_poly, int32_t n_points,
+                              const float *x, const float *y, float min_area, uint8_t *keep,
+                              float *dir, void *stream);
+
 /* Re-point the observation outputs (obs_ego, obs_partner, partner_mask, obs_road,
  * road_idx, lidar, lidar_hit; the other fields of `bufs` are ignored) so that the next
  * calls write the observation straight into, e.g., step t of a caller's rollout buffer.

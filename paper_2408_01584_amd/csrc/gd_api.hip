@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -669,6 +670,52 @@ gd_status gd_decimate(const int32_t *poly_off, int32_t n_poly, int32_t n_points,
     if (((uintptr_t)workspace % 256) != 0) return fail(GD_E_ARG, "workspace must be 256-byte aligned");
     HIP_TRY(launch_decimate_impl(poly_off, n_poly, n_points, x, y, min_area, keep, dir, workspace,
                                  (hipStream_t)stream),
+            "decimation launch");
+    return GD_OK;
+}
+
+// ---- allocation-free decimation: the workspace of at most
+// GD_DECIMATE_NOALLOC_MAX_POINTS points lives in a static device array.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in): the device
+// address of each GPU's copy is looked up once per device and kept.
+namespace {
+constexpr size_t kNoAllocScratchBytes = (size_t)GD_DECIMATE_NOALLOC_MAX_POINTS * 4 * 3;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static gd_status scratch_of_current_device(void **out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(GD_E_UNSUPPORTED, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+        if (!p || ((uintptr_t)p % 256) != 0) return fail(GD_E_HIP, "scratch array at an unusable address %p", p);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GD_OK;
+}
+
+gd_status gd_decimate_noalloc(const int32_t *poly_off, int32_t n_poly, int32_t n_points, const float *x,
+                              const float *y, float min_area, uint8_t *keep, float *dir, void *stream) {
+    if (n_poly < 0 || n_points < 0) return fail(GD_E_ARG, "n_poly and n_points must be >= 0");
+    if (n_points > GD_DECIMATE_NOALLOC_MAX_POINTS)
+        return fail(GD_E_SIZE, "n_points = %d exceeds the allocation-free limit of %d points", n_points,
+                    GD_DECIMATE_NOALLOC_MAX_POINTS);
+    if (!(min_area >= 0.0f) || !std::isfinite(min_area)) return fail(GD_E_ARG, "min_area must be finite and >= 0");
+    if (n_poly == 0 || n_points == 0) return GD_OK;
+    if (!poly_off || !x || !y || !keep || !dir) return fail(GD_E_ARG, "NULL buffer");
+    if (decimate_ws_offset(n_points, 3) > kNoAllocScratchBytes) return fail(GD_E_SIZE, "scratch too small");
+    void *ws = nullptr;
+    gd_status st = scratch_of_current_device(&ws);
+    if (st != GD_OK) return st;
+    HIP_TRY(launch_decimate_impl(poly_off, n_poly, n_points, x, y, min_area, keep, dir, ws, (hipStream_t)stream),
             "decimation launch");
     return GD_OK;
 }

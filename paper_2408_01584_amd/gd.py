@@ -23,7 +23,7 @@ GD_AUTO_RESET, GD_TERMINATE_ON_COLLISION, GD_CHECK_FINITE, GD_USE_GRAPH = 1, 2, 
 
 ENTRY_POINTS = ("gd_partner_slots", "gd_workspace_size", "gd_create", "gd_reset", "gd_step",
                 "gd_obs", "gd_rollout_fwd", "gd_rollout_bwd", "gd_invert_actions",
-                "gd_decimate_workspace_size", "gd_decimate",
+                "gd_decimate_workspace_size", "gd_decimate", "gd_decimate_noalloc",
                 "gd_set_obs_buffers", "gd_set_timing",
                 "gd_get_timing", "gd_check", "gd_destroy", "gd_last_error")
 GD_ROAD_AUTO, GD_ROAD_LDS, GD_ROAD_GLOBAL = 0, 1, 2
@@ -31,6 +31,7 @@ GD_ROAD_LANE, GD_ROAD_EDGE, GD_META_LAST = 0, 1, 1 << 8
 GD_DYN_BICYCLE, GD_DYN_DELTA = 0, 1
 GD_PHASE_STEP, GD_PHASE_LIDAR, GD_PHASE_ROLLOUT_FWD, GD_PHASE_ROLLOUT_BWD, GD_PHASE_INVERT = range(5)
 GD_NUM_PHASES = 5
+GD_DECIMATE_NOALLOC_MAX_POINTS = 1 << 22
 
 
 class GDError(RuntimeError):
@@ -84,6 +85,7 @@ def lib():
             "gd_invert_actions": [vp, vp, i32, vp, vp],
             "gd_decimate_workspace_size": [i32, szp],
             "gd_decimate": [vp, i32, i32, vp, vp, C.c_float, vp, vp, vp, C.c_size_t, vp],
+            "gd_decimate_noalloc": [vp, i32, i32, vp, vp, C.c_float, vp, vp, vp],
             "gd_set_obs_buffers": [vp, C.POINTER(gd_buffers)],
             "gd_set_timing": [vp, i32],
             "gd_get_timing": [vp, vp, vp],
@@ -172,6 +174,13 @@ def gd_decimate(poly_off_ptr: int, n_poly: int, n_points: int, x_ptr: int, y_ptr
     _check(lib().gd_decimate(C.c_void_p(poly_off_ptr), n_poly, n_points, C.c_void_p(x_ptr),
                              C.c_void_p(y_ptr), min_area, C.c_void_p(keep_ptr), C.c_void_p(dir_ptr),
                              C.c_void_p(ws_ptr), ws_bytes, C.c_void_p(stream)))
+
+
+def gd_decimate_noalloc(poly_off_ptr: int, n_poly: int, n_points: int, x_ptr: int, y_ptr: int,
+                        min_area: float, keep_ptr: int, dir_ptr: int, stream: int):
+    _check(lib().gd_decimate_noalloc(C.c_void_p(poly_off_ptr), n_poly, n_points, C.c_void_p(x_ptr),
+                                     C.c_void_p(y_ptr), min_area, C.c_void_p(keep_ptr),
+                                     C.c_void_p(dir_ptr), C.c_void_p(stream)))
 
 
 def gd_set_obs_buffers(sim, bufs: gd_buffers):

@@ -159,3 +159,20 @@ def test_decimate_argument_checks(G):
         assert e.value.status == status, (npoly, npts, area, wsb)
     # nothing to do: returns at once
     G.gd_decimate(0, 0, 0, 0, 0, 0.1, 0, 0, 0, 0, 0)
+
+
+def test_decimate_noalloc_argument_checks(G):
+    """Host-side validation of the allocation-free decimation (no device call is made):
+    sizes beyond its limit are refused before anything else."""
+    fake = 1 << 20  # never dereferenced: every call below fails before any device work
+    lim = G.GD_DECIMATE_NOALLOC_MAX_POINTS
+    cases = [((fake, 2, lim + 1), 0.1, G.GD_E_SIZE), ((fake, -1, 10), 0.1, G.GD_E_ARG),
+             ((fake, 2, -5), 0.1, G.GD_E_ARG), ((fake, 2, 1000), float("inf"), G.GD_E_ARG),
+             ((fake, 2, 1000), -1.0, G.GD_E_ARG), ((0, 2, 1000), 0.1, G.GD_E_ARG)]
+    for (po, npoly, npts), area, status in cases:
+        with pytest.raises(G.GDError) as e:
+            G.gd_decimate_noalloc(po, npoly, npts, fake, fake, area, fake, fake, 0)
+        assert e.value.status == status, (npoly, npts, area)
+        if status == G.GD_E_SIZE:
+            assert "exceeds" in str(e.value)
+    G.gd_decimate_noalloc(0, 0, 0, 0, 0, 0.1, 0, 0, 0)
