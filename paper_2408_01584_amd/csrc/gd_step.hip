@@ -2,9 +2,9 @@
 //
 //   phase 1  dynamics of the alive agents: bicycle model (App. B) or the simplified model
 //            (Sec. 3.2 "Agent dynamics")
-//   phase 2  collisions of the alive agents, one wave per agent: against the other alive
-//            and the parked agents (oriented boxes) and, except for pedestrians, against
-//            the road-edge segments of the grid cells under the box -- Sec. 3.1, Sec. 3.2
+//   phase 2  collisions of the alive agents: each pair of agents tested once (oriented
+//            boxes; parked agents are obstacles) and, except for pedestrians, the road-edge
+//            segments of the grid cells under each box -- Sec. 3.1, Sec. 3.2
 //   phase 3  goal, reward, done, world done; auto-reset from the snapshot, agents that
 //            start near their goal parked (Sec. 3.2 "Rewards", "Termination", "Sharp
 //            edges")
@@ -186,7 +186,6 @@ template <int NB, int RM>
 __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ int s_next_agent;  // phase 5 work counter
-    __shared__ int s_next_coll;   // phase 2 work counter
     int *s_next = &s_next_agent;
     constexpr bool STAGED = RM == kRoadLds;
     constexpr bool IDX16 = RM != kRoadGlobal32;
@@ -237,7 +236,6 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
 
     const WorldGrid g = a.grid[w];
     const int ncell = g.nx * g.ny;
-    if (tid == 0) s_next_coll = 0;  // published by the barrier that ends phase 1
     // phases 0 and 1 share one memory round trip: each thread issues the loads of its
     // first agent and of its share of the staging copies before its first LDS store
     int t = a.t[w];
@@ -358,73 +356,72 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
 
     bool do_reset = false, keep_outcome = false;
     if (mode == kModeStep) {
-        // phase 2: collisions, one wave per alive agent i: lanes over the other agents
-        // (oriented boxes), then lanes over the edge segments keyed in the grid cells under
-        // the box (segments are keyed by their first point: widen by the longest segment)
+        // phase 2: collisions of the alive agents with each other and with the parked ones
+        // (oriented boxes), and, except for pedestrians, with road-edge segments.
+        // Agent pairs: a wave takes agent i (wave-uniform), its lanes the agents j > i, so
+        // that each pair is tested once (the separating-axis test is symmetric) and a hit
+        // marks every alive agent of the pair.  Edge segments: a group of `tpa` lanes per
+        // alive agent runs over the segments keyed in the grid cells under its box
+        // (segments are keyed by their first point: the box is widened by the longest).
         {
-            const int *ecs = c.edge_cap ? secells : a.ecell_start + (size_t)w * kCellStride;
-            const float4 *es = c.edge_cap ? sedge : a.eseg + r0;
-            // each wave starts with agent `wid`, then takes the next unclaimed one
-            auto next_coll = [&]() {
-                int v = 0;
-                if (lane == 0) v = atomicAdd(&s_next_coll, 1);
-                return nwaves + __builtin_amdgcn_readfirstlane(v);
-            };
-            for (int i = wid; i < n; i = next_coll()) {
-                if (!(wave_uniform(sf[i]) & GD_FLAG_ALIVE)) continue;
-                // pedestrians may cross road edges (Sec. 3.2 "Termination")
-                const bool ped = a.cls && a.cls[a0 + i] == GD_CLASS_PEDESTRIAN;
+            for (int i = wid; i < n - 1; i += nwaves) {
+                const int fi = wave_uniform(sf[i]);
+                if (!(fi & (GD_FLAG_ALIVE | GD_FLAG_STATIC))) continue;
+                const bool alive_i = (fi & GD_FLAG_ALIVE) != 0;
                 const float xi = wave_uniform(sx[i]), yi = wave_uniform(sy[i]);
                 const float ci = wave_uniform(sc[i]), si = wave_uniform(ss[i]);
                 const float Li = wave_uniform(sL[i]), Wi = wave_uniform(sW[i]);
                 const float di = sqrtf(Li * Li + Wi * Wi);
-                bool ha = false;
-                for (int j = lane; j < n; j += kWave) {
-                    if (j == i || !(sf[j] & (GD_FLAG_ALIVE | GD_FLAG_STATIC))) continue;
+                bool hit_i = false;
+                for (int j = i + 1 + lane; j < n; j += kWave) {
+                    const int fj = sf[j];
+                    // a pair needs an alive agent; a parked agent is an obstacle only
+                    if (!(fj & (alive_i ? (GD_FLAG_ALIVE | GD_FLAG_STATIC) : GD_FLAG_ALIVE))) continue;
                     const float dx = sx[j] - xi, dy = sy[j] - yi;
                     const float rr = 0.5f * (di + sqrtf(sL[j] * sL[j] + sW[j] * sW[j])) + 1e-3f;
                     if (dx * dx + dy * dy > rr * rr) continue;
-                    if (sat_box_box(dx, dy, ci, si, Li, Wi, sc[j], ss[j], sL[j], sW[j]) < 0.0f) ha = true;
+                    if (sat_box_box(dx, dy, ci, si, Li, Wi, sc[j], ss[j], sL[j], sW[j]) < 0.0f) {
+                        hit_i = true;
+                        if (fj & GD_FLAG_ALIVE) atomicOr(&scoll[j], (int)GD_FLAG_COLL_AGENT);
+                    }
                 }
-                const bool agent_hit = __ballot(ha) != 0ull;
+                if (alive_i && __ballot(hit_i) != 0ull && lane == 0) atomicOr(&scoll[i], (int)GD_FLAG_COLL_AGENT);
+            }
 
-                const float hL = 0.5f * Li, hW = 0.5f * Wi;
+            const int *ecs = c.edge_cap ? secells : a.ecell_start + (size_t)w * kCellStride;
+            const float4 *es = c.edge_cap ? sedge : a.eseg + r0;
+            // lanes per agent: a power of two, at most a wave, all agents covered by one
+            // pass of the workgroup when they fit
+            int tpa = kWave;
+            while (tpa > 1 && tpa * n > bs) tpa >>= 1;
+            const int sub = tid & (tpa - 1);
+            const int ngroups = bs / tpa;
+            const float m = g.max_seg + 1e-3f;
+            for (int i = tid / tpa; i < n; i += ngroups) {
+                if (!(sf[i] & GD_FLAG_ALIVE)) continue;
+                // pedestrians may cross road edges (Sec. 3.2 "Termination")
+                if (a.cls && a.cls[a0 + i] == GD_CLASS_PEDESTRIAN) continue;
+                const float xi = sx[i], yi = sy[i], ci = sc[i], si = ss[i];
+                const float hL = 0.5f * sL[i], hW = 0.5f * sW[i];
                 const float ex = fabsf(ci) * hL + fabsf(si) * hW;
                 const float ey = fabsf(si) * hL + fabsf(ci) * hW;
-                const float m = g.max_seg + 1e-3f;
                 const int cx0 = cell_coord(xi - ex - m, g.ox, g.inv_cs, g.nx);
                 const int cx1 = cell_coord(xi + ex + m, g.ox, g.inv_cs, g.nx);
                 const int cy0 = cell_coord(yi - ey - m, g.oy, g.inv_cs, g.ny);
                 const int cy1 = cell_coord(yi + ey + m, g.oy, g.inv_cs, g.ny);
-                // the cells' segment ranges of each row, concatenated (lane = row), so that
-                // the segments of all rows fill the lanes together
-                const int nre = ped ? 0 : cy1 - cy0 + 1;  // at most kGridAxis
-                int e0 = 0, e1 = 0;
-                if (lane < nre) {
-                    e0 = ecs[(cy0 + lane) * g.nx + cx0];
-                    e1 = ecs[(cy0 + lane) * g.nx + cx1 + 1];
-                }
-                const int elen = e1 - e0;
-                const int eend = wave_incl_scan(elen);
-                const int EM = __builtin_amdgcn_readlane(eend, kWave - 1);
-                const int eoff = eend - elen;
-                const int edel = e0 - eoff;
                 bool hit = false;
-                int er = 0;
-                for (int base = 0; base < EM && !hit; base += kWave) {
-                    const int q = span_point(base, lane, eend, eoff, edel, nre, er);
-                    bool h = false;
-                    if (base + lane < EM) {
+                for (int r = cy0; r <= cy1; r++) {
+                    const int e0 = ecs[r * g.nx + cx0], e1 = ecs[r * g.nx + cx1 + 1];
+                    for (int q = e0 + sub; q < e1; q += tpa) {
                         const float4 e = es[q];
                         const float x0 = e.x - xi, y0 = e.y - yi, x1 = e.z - xi, y1 = e.w - yi;
-                        if (!(fminf(x0, x1) > ex || fmaxf(x0, x1) < -ex || fminf(y0, y1) > ey ||
-                              fmaxf(y0, y1) < -ey))
-                            h = sat_box_seg(ci, si, hL, hW, x0, y0, x1, y1) < 0.0f;
+                        if (fminf(x0, x1) > ex || fmaxf(x0, x1) < -ex || fminf(y0, y1) > ey ||
+                            fmaxf(y0, y1) < -ey)
+                            continue;
+                        if (sat_box_seg(ci, si, hL, hW, x0, y0, x1, y1) < 0.0f) hit = true;
                     }
-                    hit = __ballot(h) != 0ull;
                 }
-                if (lane == 0)
-                    scoll[i] = (agent_hit ? (int)GD_FLAG_COLL_AGENT : 0) | (hit ? (int)GD_FLAG_COLL_EDGE : 0);
+                if (hit) atomicOr(&scoll[i], (int)GD_FLAG_COLL_EDGE);
             }
         }
         __syncthreads();
