@@ -29,7 +29,8 @@
 //   d. the candidates of the bins up to that one are scattered bin by bin with their keys;
 //   e. rank = first slot of the bin + bin mates with smaller (d2, index): an exact order
 //      by (d2, index);
-//   f. the K slots are written in order as float4 rows (x', y', dir', type) + index.
+//   f. each ranked point writes its slot, a float4 row (x', y', dir', type) + index, at
+//      once (no slot table).
 // A cut bin too large for the staging array is resolved element by element by a wave
 // min-reduction (exact, slow, for pathological point clusters only).
 #include "gd_internal.h"
@@ -169,11 +170,9 @@ struct PointIndex<true> {
 //   cand  ccap entries   (bin, point) of every point within the radius
 //   skey  scap floats    keys of the staged points (bins up to the cut bin)
 //   sq    scap indices   their points
-//   perm  K indices      point of each output slot
 __host__ __device__ inline size_t wave_lds_bytes(int NB, int K, int ccap, bool idx16) {
     const size_t ib = idx16 ? 2 : 4, cb = idx16 ? 4 : 8;
-    const size_t b = (size_t)NB * 4 + (size_t)ccap * cb + (size_t)stage_cap(K) * (4 + ib) +
-                     (size_t)K * ib;
+    const size_t b = (size_t)NB * 4 + (size_t)ccap * cb + (size_t)stage_cap(K) * (4 + ib);
     return (b + 15) / 16 * 16;
 }
 
@@ -232,7 +231,6 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     cand_t *cand = reinterpret_cast<cand_t *>(hist + NB);
     float *skey = reinterpret_cast<float *>(cand + ccap);
     idx_t *sq = reinterpret_cast<idx_t *>(skey + scap);
-    idx_t *perm = sq + scap;
 
     const WorldGrid g = a.grid[w];
     const int ncell = g.nx * g.ny;
@@ -364,28 +362,46 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
         // alive agent runs over the segments keyed in the grid cells under its box
         // (segments are keyed by their first point: the box is widened by the longest).
         {
-            for (int i = wid; i < n - 1; i += nwaves) {
-                const int fi = wave_uniform(sf[i]);
-                if (!(fi & (GD_FLAG_ALIVE | GD_FLAG_STATIC))) continue;
-                const bool alive_i = (fi & GD_FLAG_ALIVE) != 0;
-                const float xi = wave_uniform(sx[i]), yi = wave_uniform(sy[i]);
-                const float ci = wave_uniform(sc[i]), si = wave_uniform(ss[i]);
-                const float Li = wave_uniform(sL[i]), Wi = wave_uniform(sW[i]);
-                const float di = sqrtf(Li * Li + Wi * Wi);
-                bool hit_i = false;
-                for (int j = i + 1 + lane; j < n; j += kWave) {
+            // four agents i per wave at a time, their data read together, against lane j
+            constexpr int PI = 4;
+            for (int i0 = wid; i0 < n - 1; i0 += PI * nwaves) {
+                int fi[PI];
+                float xi[PI], yi[PI], ci[PI], si[PI], Li[PI], Wi[PI];
+#pragma unroll
+                for (int k = 0; k < PI; k++) {
+                    const int i = min(i0 + k * nwaves, n - 1);
+                    fi[k] = i0 + k * nwaves < n - 1 ? wave_uniform(sf[i]) : 0;
+                    xi[k] = wave_uniform(sx[i]);
+                    yi[k] = wave_uniform(sy[i]);
+                    ci[k] = wave_uniform(sc[i]);
+                    si[k] = wave_uniform(ss[i]);
+                    Li[k] = wave_uniform(sL[i]);
+                    Wi[k] = wave_uniform(sW[i]);
+                }
+                bool hit[PI] = {};
+                for (int j = lane; j < n; j += kWave) {
                     const int fj = sf[j];
-                    // a pair needs an alive agent; a parked agent is an obstacle only
-                    if (!(fj & (alive_i ? (GD_FLAG_ALIVE | GD_FLAG_STATIC) : GD_FLAG_ALIVE))) continue;
-                    const float dx = sx[j] - xi, dy = sy[j] - yi;
-                    const float rr = 0.5f * (di + sqrtf(sL[j] * sL[j] + sW[j] * sW[j])) + 1e-3f;
-                    if (dx * dx + dy * dy > rr * rr) continue;
-                    if (sat_box_box(dx, dy, ci, si, Li, Wi, sc[j], ss[j], sL[j], sW[j]) < 0.0f) {
-                        hit_i = true;
-                        if (fj & GD_FLAG_ALIVE) atomicOr(&scoll[j], (int)GD_FLAG_COLL_AGENT);
+                    const float xj = sx[j], yj = sy[j], cj = sc[j], sj = ss[j], Lj = sL[j], Wj = sW[j];
+                    const float dj = sqrtf(Lj * Lj + Wj * Wj);
+#pragma unroll
+                    for (int k = 0; k < PI; k++) {
+                        // a pair needs an alive agent; a parked agent is an obstacle only
+                        const bool alive_i = (fi[k] & GD_FLAG_ALIVE) != 0;
+                        if (j <= i0 + k * nwaves || !(fi[k] & (GD_FLAG_ALIVE | GD_FLAG_STATIC))) continue;
+                        if (!(fj & (alive_i ? (GD_FLAG_ALIVE | GD_FLAG_STATIC) : GD_FLAG_ALIVE))) continue;
+                        const float dx = xj - xi[k], dy = yj - yi[k];
+                        const float rr = 0.5f * (sqrtf(Li[k] * Li[k] + Wi[k] * Wi[k]) + dj) + 1e-3f;
+                        if (dx * dx + dy * dy > rr * rr) continue;
+                        if (sat_box_box(dx, dy, ci[k], si[k], Li[k], Wi[k], cj, sj, Lj, Wj) < 0.0f) {
+                            hit[k] = true;
+                            if (fj & GD_FLAG_ALIVE) atomicOr(&scoll[j], (int)GD_FLAG_COLL_AGENT);
+                        }
                     }
                 }
-                if (alive_i && __ballot(hit_i) != 0ull && lane == 0) atomicOr(&scoll[i], (int)GD_FLAG_COLL_AGENT);
+#pragma unroll
+                for (int k = 0; k < PI; k++)
+                    if ((fi[k] & GD_FLAG_ALIVE) && __ballot(hit[k]) != 0ull && lane == 0)
+                        atomicOr(&scoll[i0 + k * nwaves], (int)GD_FLAG_COLL_AGENT);
             }
 
             const int *ecs = c.edge_cap ? secells : a.ecell_start + (size_t)w * kCellStride;
@@ -398,11 +414,13 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             const int ngroups = bs / tpa;
             const float m = g.max_seg + 1e-3f;
             for (int i = tid / tpa; i < n; i += ngroups) {
-                if (!(sf[i] & GD_FLAG_ALIVE)) continue;
-                // pedestrians may cross road edges (Sec. 3.2 "Termination")
-                if (a.cls && a.cls[a0 + i] == GD_CLASS_PEDESTRIAN) continue;
+                // (every load before the first branch: one LDS round trip)
+                const int fi = sf[i];
                 const float xi = sx[i], yi = sy[i], ci = sc[i], si = ss[i];
                 const float hL = 0.5f * sL[i], hW = 0.5f * sW[i];
+                if (!(fi & GD_FLAG_ALIVE)) continue;
+                // pedestrians may cross road edges (Sec. 3.2 "Termination")
+                if (a.cls && a.cls[a0 + i] == GD_CLASS_PEDESTRIAN) continue;
                 const float ex = fabsf(ci) * hL + fabsf(si) * hW;
                 const float ey = fabsf(si) * hL + fabsf(ci) * hW;
                 const int cx0 = cell_coord(xi - ex - m, g.ox, g.inv_cs, g.nx);
@@ -766,12 +784,18 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
 
         // e. rank inside each bin by (d2, world-local index): count the bin mates with a
         //    smaller key (branch-free); exact key ties are ordered by index in a second
-        //    pass that only lanes with a tie take
+        //    pass that only lanes with a tie take.  f. each ranked point writes its slot
+        //    (x', y', dir', type) + index at once.
         const int nstaged = overflow ? cut_start : need;
+        const int direct_end = overflow ? cut_start : nsel;
+        // road directions lie in [-pi, pi]: against the wrapped heading, one correction
+        const float yaw_w = wrap_pi(yaw);
         float kk = -1.0f;  // key of slot K - 1, on the lane that ranks it
         for (int p = lane; p < nstaged; p += kWave) {
             const float k = skey[p];
             const int q = sq[p];
+            const float2 pt = rxy[q];
+            const float2 x2 = aux[q];
             const int b = bin_of(k, bscale, NB);
             const int lo = b > 0 ? hist[b - 1] : 0;
             const int hi = hist[b];
@@ -783,15 +807,28 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
                 rank += (int)(ko < k);
                 rank_le += (int)(ko <= k);
             }
+            const int bits = __float_as_int(x2.y);
             if (rank_le - rank > 1) {
-                const int my_idx = __float_as_int(aux[q].y) & 0xffffff;
+                const int my_idx = bits & 0xffffff;
                 for (int m = lo; m < hi; m++)
                     if (m != p && skey[m] == k)
                         rank += (int)((__float_as_int(aux[sq[m]].y) & 0xffffff) < my_idx);
             }
             const int fin = lo + rank;
-            if (fin < K) perm[fin] = (idx_t)q;
+            if (fin < direct_end) {
+                const float dx = pt.x - px, dy = pt.y - py;
+                float dd = x2.x - yaw_w;
+                dd = dd >= 3.14159265358979323846f ? dd - 6.283185307179586f : dd;
+                dd = dd < -3.14159265358979323846f ? dd + 6.283185307179586f : dd;
+                out[fin] = make_float4(csy * dx + sny * dy, -sny * dx + csy * dy, dd, (float)((unsigned)bits >> 24));
+                oidx[fin] = bits & 0xffffff;
+            }
             kk = fin == K - 1 ? k : kk;
+        }
+        // slots beyond the points in the radius
+        for (int s = nsel + lane; s < K; s += kWave) {
+            out[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+            oidx[s] = -1;
         }
         // the K-th key (R^2 when fewer than K points are in the radius), kept for the next
         // step's pruned radius
@@ -825,42 +862,6 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
                                          wrap_pi(a.rdir[r0 + idx] - yaw),
                                          (float)(a.rmeta[r0 + idx] & 0xff));
                     oidx[s] = idx;
-                }
-            }
-        }
-        wave_sync();
-
-        // f. the K slots in order, four per lane at a time so that their point loads
-        //    are in flight together
-        const int direct_end = overflow ? cut_start : nsel;
-        // road directions lie in [-pi, pi]: against the wrapped heading, one correction
-        const float yaw_w = wrap_pi(yaw);
-        for (int s0 = 0; s0 < K; s0 += 4 * kWave) {
-            float2 pt[4], x2[4];
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const int s = s0 + u * kWave + lane;
-                if (s < direct_end) {
-                    const int q = min((int)perm[s], nr - 1);  // (a slot always holds a point)
-                    pt[u] = rxy[q];
-                    x2[u] = aux[q];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const int s = s0 + u * kWave + lane;
-                if (s < direct_end) {
-                    const int bits = __float_as_int(x2[u].y);
-                    const float dx = pt[u].x - px, dy = pt[u].y - py;
-                    float dd = x2[u].x - yaw_w;
-                    dd = dd >= 3.14159265358979323846f ? dd - 6.283185307179586f : dd;
-                    dd = dd < -3.14159265358979323846f ? dd + 6.283185307179586f : dd;
-                    out[s] = make_float4(csy * dx + sny * dy, -sny * dx + csy * dy, dd,
-                                         (float)((unsigned)bits >> 24));
-                    oidx[s] = bits & 0xffffff;
-                } else if (s >= nsel && s < K) {
-                    out[s] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    oidx[s] = -1;
                 }
             }
         }
