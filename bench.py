@@ -227,6 +227,13 @@ def main():
         "step": {"launch": "graph" if args.graph else "direct",
                  "observed_agent_fraction": round(vis_frac, 4),
                  "active_agent_steps_per_s": round(value * vis_frac, 1)},
+        # the paper's own figure, for context only: another simulator implementation, other
+        # hardware and other scenes (vs_baseline stays null)
+        "context": {"paper_peak_agent_steps_per_s": 2.3e6,
+                    "paper_source": "Sec. 4.1, Fig. 3 (peak ASPS over the number of worlds)",
+                    "paper_hardware": "NVIDIA consumer and datacenter GPUs (RTX 4080 / A100 class); "
+                                      "precision not stated",
+                    "paper_workload": "Waymo Open Motion Dataset scenes, radius-filter observation"},
     }
     if args.copy_calibration:
         a = torch.empty(COPY_ELEMS, dtype=torch.float32, device=dev)
