@@ -113,7 +113,7 @@ __device__ __forceinline__ void row_span(const WorldGrid &g, const int *cst, int
         q0 = q1 = 0;
         return;
     }
-    float hw = sqrtf(fmaxf(R * R - dy * dy, 0.0f)) + marg;
+    float hw = __builtin_amdgcn_sqrtf(fmaxf(R * R - dy * dy, 0.0f)) + marg;  // (1 ulp, within marg)
     int c0 = cell_coord(px - hw, g.ox, g.inv_cs, g.nx);
     int c1 = cell_coord(px + hw, g.ox, g.inv_cs, g.nx);
     q0 = cst[r * g.nx + c0];
@@ -632,9 +632,11 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
         float Re = 0.0f, bscale = 0.0f;
         int nrows = 0, q0 = 0, q1 = 0, ncand = 0;
         for (;;) {
-            Re = sqrtf(R2e);
-            bscale = ((float)NB - 0.5f) / R2e;
-            for (int b = lane; b < NB; b += kWave) hist[b] = 0;
+            // Re rounded up past the 1-ulp error of the hardware square root; the bin scale
+            // from the hardware reciprocal (1 ulp): k * bscale < NB still holds for k <= R2e
+            Re = __builtin_amdgcn_sqrtf(R2e) * 1.000001f;
+            bscale = ((float)NB - 0.5f) * __builtin_amdgcn_rcpf(R2e);
+            for (int b = lane; b < NB / 4; b += kWave) reinterpret_cast<int4 *>(hist)[b] = make_int4(0, 0, 0, 0);
             // a. candidate rows: lane r holds the span [q0, q1) of grid row rlo + r and
             //    its place [end - len, end) in the concatenation of all the spans
             const int rlo = cell_coord(py - Re, g.oy, g.inv_cs, g.ny);
@@ -669,11 +671,13 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
                 for (int u = 0; u < SU; u++) {
                     const float k = key32(px, py, pt[u].x, pt[u].y);
                     const bool in = base + u * kWave + lane < M && k <= R2e;
-                    const int bn = bin_of(k, bscale, NB);
-                    if (in) atomicAdd(&hist[bn], 1);
                     const unsigned long long bal = __ballot(in);
-                    const int pos = ncand + lane_prefix(bal);
-                    if (in && pos < ccap) cand[pos] = ((cand_t)bn << SH) | (cand_t)qv[u];
+                    if (in) {
+                        const int bn = bin_of(k, bscale, NB);
+                        atomicAdd(&hist[bn], 1);
+                        const int pos = ncand + lane_prefix(bal);
+                        if (pos < ccap) cand[pos] = ((cand_t)bn << SH) | (cand_t)qv[u];
+                    }
                     ncand += __popcll(bal);
                 }
             }
