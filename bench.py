@@ -26,7 +26,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12  # MI355X HBM3E, B/s
+# Vector-ALU ceiling of MI355X: the published FP32 vector rate, 157.3 TFLOP/s = 256 CUs x
+# 2.4 GHz x 256 FLOP per clock, i.e. 128 lane-operations per CU per clock counting an FMA as
+# one operation (two wave64 instructions per CU per clock).  Measured on the part: simple
+# integer and min/max instructions issue at up to 1.4 wave64 instructions per CU per clock,
+# FP32 FMA (without packed FP32, which this build never emits) at 0.9
+VALU_PEAK = 256 * 128 * 2.4e9
 WORKLOAD_TAG = "256w_64a_4000r_k200"
+WORKLOADS = {0: "1w_8a_500r_k64", 1: WORKLOAD_TAG, 2: "1024w_uneven", 3: "512w_32a_2000r_k64",
+             4: "4096w_64a_6000r_n30"}
 PMC_FILE = os.path.join(ROOT, "profiles", "k_step_%s_hbm_counters.json" % WORKLOAD_TAG)
 COPY_ELEMS = 1 << 28  # float32 elements of the calibration copy (1 GiB each way)
 
@@ -52,6 +60,14 @@ def parse():
                     help="1 (default): the headline workload; 0, 2, 3, 4: the secondary "
                          "workloads (latency, uneven batch, differentiable rollout, LIDAR + "
                          "rollout at 4096 worlds), one JSON line each")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="no timing: a few steps of workload --config (and, for 3 and 4, two rollouts "
+                         "forward + backward) for a profiler to record; the 4096-world workload repeats "
+                         "its first 64 worlds (same sizes, 1/64 of the generation time)")
+    ap.add_argument("--ingest-sq", nargs="+", metavar="ARG",
+                    help="KERNEL TAG FOLDER SOURCE...: turn a rocprofv3 --pmc folder (SQ_INSTS_VALU, "
+                         "SQ_ACTIVE_INST_VALU, ...) into the instruction-counter record of KERNEL on "
+                         "workload TAG, keyed by the digest of the SOURCE files, then exit")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc output folders (FETCH_SIZE, WRITE_SIZE) of a "
                          "--copy-calibration run into the HBM-traffic record, then exit")
@@ -109,8 +125,68 @@ def ingest_counters(fetch_dir, write_dir):
     print(json.dumps(rec))
 
 
+def ingest_sq(kernel, tag, folder, *sources):
+    """Mean per dispatch of every counter in the folder for `kernel` (dispatches whose
+    name contains it), written to profiles/<kernel>_<tag>_sq_counters.json."""
+    import csv
+    import glob
+    per = {}
+    for f in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+        for row in csv.DictReader(open(f)):
+            if kernel not in row["Kernel_Name"]:
+                continue
+            d = per.setdefault((f, row["Dispatch_Id"]), {})
+            d[row["Counter_Name"]] = d.get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
+    if not per:
+        raise SystemExit("no %s dispatches under %s" % (kernel, folder))
+    names = sorted({k for d in per.values() for k in d})
+    mean = {k: sum(d.get(k, 0.0) for d in per.values()) / len(per) for k in names}
+    rec = {"kernel": kernel, "workload": tag, "sources": list(sources),
+           "source_digest": source_digest(*sources), "dispatches": len(per),
+           "counters_per_launch": mean,
+           "valu_insts_per_launch": mean.get("SQ_INSTS_VALU")}
+    with open(os.path.join(ROOT, "profiles", "%s_%s_sq_counters.json" % (kernel, tag)), "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+    print(json.dumps(rec))
+
+
+def profile_run(args):
+    import torch
+
+    from paper_2408_01584_amd import scenes as S
+    from paper_2408_01584_amd.sim import Sim
+    c = args.config
+    torch.cuda.set_device(0)
+    if c == 4:
+        spec = S.CONFIGS[4]
+        base = [S.make_world(4, w, spec.worlds) for w in range(64)]
+        scene = S.assemble(4, [base[i % 64] for i in range(spec.worlds)], spec.params,
+                           world_ids=[i % 64 for i in range(spec.worlds)])
+    else:
+        scene = S.make_scene(c)
+    print("[bench] profile run: workload %d, %d agents" % (c, scene.num_agents), file=sys.stderr, flush=True)
+    sim = Sim(scene)
+    T = S.CONFIGS[c].steps
+    acts = torch.as_tensor(S.make_actions(c, T + 4, scene.num_agents), device="cuda")
+    for k in range(min(args.steps, T + 4)):
+        sim.step(acts[k])
+    if c in (3, 4):
+        ra = acts[:T].contiguous()
+        for _ in range(2):
+            r, ck = sim.rollout_fwd(ra, 10)
+            sim.rollout_bwd(ra, ck, torch.ones_like(r), 10)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_run": c, "steps": min(args.steps, T + 4)}), flush=True)
+
+
 def main():
     args = parse()
+    if args.profile_run:
+        profile_run(args)
+        return
+    if args.ingest_sq:
+        ingest_sq(*args.ingest_sq)
+        return
     if args.ingest_counters:
         ingest_counters(*args.ingest_counters)
         return
@@ -248,6 +324,65 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def edge_segments(scene) -> int:
+    """Road-edge segments of a scene: consecutive edge points of one polyline."""
+    import numpy as np
+    m = np.asarray(scene.road_meta)
+    is_edge = (m & 0xFF) == 1
+    last = (m & 0x100) != 0
+    return int((is_edge[:-1] & is_edge[1:] & ~last[:-1]).sum())
+
+
+def step_bytes(scene, slots):
+    """Algorithmic bytes of one step-kernel launch: per agent state read + write 32,
+    length/width/goal 16, action 8, flags 2, reward 4, ego 32, road observation 20 K;
+    25 per partner slot (24 B features + mask); each world's road read once (16 B per
+    point)."""
+    p = scene.params
+    A = scene.num_agents
+    return A * (32 + 16 + 8 + 2 + 4 + 32 + 20 * p.top_k) + 25 * slots + 16 * scene.num_road
+
+
+def lidar_bytes(scene):
+    """Algorithmic bytes of one LIDAR launch: per agent 8 B per ray written (distance,
+    hit type) and its pose and box read (24 B); each world's edge segments read once
+    (16 B)."""
+    return scene.num_agents * (8 * scene.params.lidar_rays + 24) + 16 * edge_segments(scene)
+
+
+def counters_record(kernel, tag):
+    """Instruction counters of `kernel` on workload `tag` from profiles/, when they were
+    taken on the current kernel source."""
+    f = os.path.join(ROOT, "profiles", "%s_%s_sq_counters.json" % (kernel, tag))
+    if not os.path.exists(f):
+        return None
+    rec = json.load(open(f))
+    if rec.get("source_digest") != source_digest(*rec.get("sources", [])):
+        return None
+    return rec
+
+
+def alu_roofline(kernel, tag, avg_ms):
+    """VALU issue rate of a kernel: wave instructions per launch (from the committed
+    counters) x 64 lanes / its average launch time, against VALU_PEAK."""
+    rec = counters_record(kernel, tag)
+    if rec is None:
+        return {"kernel": kernel, "bound": "alu", "achieved": None, "peak": VALU_PEAK / 1e12,
+                "unit": "TOP/s", "frac": None, "note": "no counters for the current source"}
+    ops = rec["valu_insts_per_launch"] * 64
+    ach = ops / (avg_ms / 1e3)
+    return {"kernel": kernel, "bound": "alu", "achieved": round(ach / 1e12, 3), "peak": VALU_PEAK / 1e12,
+            "unit": "TOP/s", "frac": round(ach / VALU_PEAK, 4), "avg_launch_ms": round(avg_ms, 5),
+            "valu_wave_insts_per_launch": rec["valu_insts_per_launch"]}
+
+
+def hbm_roofline(kernel, nbytes, avg_ms):
+    ach = nbytes / (avg_ms / 1e3)
+    return {"kernel": kernel, "bound": "hbm", "achieved": round(ach / 1e9, 1), "peak": HBM_PEAK / 1e9,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": int(nbytes), "avg_launch_ms": round(avg_ms, 5)}
+
+
 def _timed(fn, reps=5):
     """Median over `reps` event-timed calls of fn() on the current stream (ms)."""
     import torch
@@ -304,6 +439,25 @@ def secondary(args):
         if name == "direct":
             out["value"] = out[name]["value"]
             out["ms_per_step"] = out[name]["ms_per_step"]
+            # per-kernel launch times (HIP events around each launch), then the rooflines:
+            # the step kernel against HBM, the LIDAR kernel against HBM and VALU issue
+            from paper_2408_01584_amd import gd as G
+            sim.set_timing(True)
+            sim.get_timing()
+            run_steps(sim, T)()
+            torch.cuda.synchronize()
+            tms, tcnt = sim.get_timing()
+            sim.set_timing(False)
+            k_ms = tms[G.GD_PHASE_STEP] / max(tcnt[G.GD_PHASE_STEP], 1)
+            sb = step_bytes(scene, sim.S)
+            out["roofline"] = hbm_roofline("k_step", sb, k_ms)
+            out["roofline"]["bytes_per_agent_step"] = round(sb / A, 1)
+            if p.lidar_rays > 0:
+                l_ms = tms[G.GD_PHASE_LIDAR] / max(tcnt[G.GD_PHASE_LIDAR], 1)
+                lb = lidar_bytes(scene)
+                out["roofline_lidar"] = hbm_roofline("k_lidar", lb, l_ms)
+                out["roofline_lidar_alu"] = alu_roofline("k_lidar", WORKLOADS[c], l_ms)
+                out["roofline_step"] = hbm_roofline("k_step + k_lidar", sb + lb, ms / T)
         sim.close()
         del sim
         torch.cuda.empty_cache()
@@ -322,6 +476,17 @@ def secondary(args):
             r, ck = sim.rollout_fwd(ra, C)
             sim.rollout_bwd(ra, ck, gr, C)
         fwdbwd = _timed(fb)
+        from paper_2408_01584_amd import gd as G
+        sim.set_timing(True)
+        sim.get_timing()
+        fb()
+        torch.cuda.synchronize()
+        tms, tcnt = sim.get_timing()
+        sim.set_timing(False)
+        f_ms = tms[G.GD_PHASE_ROLLOUT_FWD] / max(tcnt[G.GD_PHASE_ROLLOUT_FWD], 1)
+        b_ms = tms[G.GD_PHASE_ROLLOUT_BWD] / max(tcnt[G.GD_PHASE_ROLLOUT_BWD], 1)
+        rollout_alu = {"fwd": alu_roofline("k_rollout_fwd", WORKLOADS[c], f_ms),
+                       "bwd": alu_roofline("k_rollout_bwd", WORKLOADS[c], b_ms)}
         torch.cuda.synchronize()
         torch.cuda.reset_peak_memory_stats()
         base = torch.cuda.memory_allocated()
@@ -335,7 +500,8 @@ def secondary(args):
             "fwd_bwd_over_fwd_time": round(fwdbwd / fwd, 3),
             "checkpoint_bytes": int(ckpt.numel() * 4),
             "checkpoint_bytes_every_step": int(T * 4 * A * 4),
-            "peak_extra_bytes_fwd_bwd": int(peak_ck)}
+            "peak_extra_bytes_fwd_bwd": int(peak_ck),
+            "roofline_alu": rollout_alu}
         sim.close()
         del sim
         torch.cuda.empty_cache()
