@@ -866,32 +866,149 @@ void or_rollout(const or_batch *b, const or_config *c, int T, const double *acti
     }
 }
 
-/* Hand-derived vector-Jacobian product of the rollout: given dJ/dr_t (grad_rewards
-   [T,A]), returns dJ/d(accel, steer)_t (grad_actions [T,A,2]) and dJ/ds_0 (grad_state0
-   [4,A], optional).  Segment choice, side, clamp and clip activity are held constant. */
-void or_rollout_vjp(const or_batch *b, const or_config *c, int T, const double *actions,
-                    const double *grad_rewards, double *grad_actions, double *grad_state0) {
-    int A = b->agent_off[b->W];
-    double dt = c->dt;
+/* Continuous observation of the differentiable rollout (Fig. 1; Sec. 3.2 "Sensor
+   modalities"), read from the state after each step: per agent its speed and its goal in
+   its own frame, then for each of its P partner slots (slot s holds the s-th other agent
+   of its world in index order) the partner's position in the agent's frame, the heading
+   difference wrapped to [-pi, pi) and the partner's speed when the partner lies within
+   the observation radius (FP64 distance, inclusive), zeros otherwise.  The rollout removes
+   no agent, so every agent is visible.  Box length and width, constant, are left out.
+   states [T+1, 4, A] as written by or_rollout; obs [T, A, 3 + 4P].  band [T, A]
+   (optional) gets 1 where a partner of the agent lies within 1e-4 m of the radius or its
+   heading difference within 1e-6 rad of the wrap (decisions at their thresholds). */
+void or_rollout_obs(const or_batch *b, const or_config *c, int T, const double *states,
+                    double *obs, uint8_t *band) {
+    const int A = b->agent_off[b->W], P = c->partners, F = 3 + 4 * P;
+    const double R = c->obs_radius;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int w = 0; w < b->W; w++) {
-        for (int i = b->agent_off[w]; i < b->agent_off[w + 1]; i++) {
-            double L = b->len[i];
-            /* forward pass, keeping the states and the segment choices */
-            double *S = (double *)malloc(sizeof(double) * 4 * (size_t)(T + 1));
-            seg_choice *SC = (seg_choice *)malloc(sizeof(seg_choice) * (size_t)(T > 0 ? T : 1));
+        const int a0 = b->agent_off[w], n = b->agent_off[w + 1] - a0;
+        for (int t = 0; t < T; t++) {
+            const double *S = states + (int64_t)(t + 1) * 4 * A;
+            for (int l = 0; l < n; l++) {
+                const int i = a0 + l;
+                const double x = S[i], y = S[A + i], th = S[2 * A + i], v = S[3 * A + i];
+                const double ct = cos(th), st = sin(th);
+                double *o = obs + ((int64_t)t * A + i) * F;
+                const double dxg = b->gx[i] - x, dyg = b->gy[i] - y;
+                o[0] = v;
+                o[1] = ct * dxg + st * dyg;
+                o[2] = -st * dxg + ct * dyg;
+                uint8_t near = 0;
+                for (int sl = 0; sl < P; sl++) {
+                    double *f = o + 3 + 4 * sl;
+                    f[0] = f[1] = f[2] = f[3] = 0.0;
+                    const int j = sl < l ? sl : sl + 1;
+                    if (j >= n) continue;
+                    const int jj = a0 + j;
+                    const double dx = S[jj] - x, dy = S[A + jj] - y;
+                    if (fabs(sqrt(dx * dx + dy * dy) - R) < OR_BAND) near = 1;
+                    if (dx * dx + dy * dy > R * R) continue;
+                    const double dyaw = wrap_angle(S[2 * A + jj] - th);
+                    if (fabs(dyaw) > OR_PI - 1e-6) near = 1;
+                    f[0] = ct * dx + st * dy;
+                    f[1] = -st * dx + ct * dy;
+                    f[2] = dyaw;
+                    f[3] = S[3 * A + jj];
+                }
+                if (band) band[(int64_t)t * A + i] = near;
+            }
+        }
+    }
+}
+
+/* Hand-derived vector-Jacobian product of the rollout: given dJ/dr_t (grad_rewards
+   [T,A]) and, optionally, dJ/dobs_t (grad_obs [T, A, 3 + 4P], the observation of
+   or_rollout_obs), returns dJ/d(accel, steer)_t (grad_actions [T,A,2]) and dJ/ds_0
+   (grad_state0 [4,A], optional).  Segment choice, side, clamp, clip activity, partner
+   masks and heading wraps are held constant.  The observation couples the agents of a
+   world (an agent's state enters its partners' observations), so the terms of every
+   observation are first gathered into per-agent, per-step increments of the adjoint of
+   the state after the step; the reverse pass of each agent then adds them. */
+void or_rollout_vjp(const or_batch *b, const or_config *c, int T, const double *actions,
+                    const double *grad_rewards, const double *grad_obs, double *grad_actions,
+                    double *grad_state0) {
+    int A = b->agent_off[b->W];
+    double dt = c->dt;
+    const int P = c->partners, F = 3 + 4 * P;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int w = 0; w < b->W; w++) {
+        const int a0 = b->agent_off[w], n = b->agent_off[w + 1] - a0;
+        /* forward pass of every agent of the world, keeping states and segment choices */
+        double *SW = (double *)malloc(sizeof(double) * 4 * (size_t)(T + 1) * (size_t)(n > 0 ? n : 1));
+        seg_choice *SCW = (seg_choice *)malloc(sizeof(seg_choice) * (size_t)(T > 0 ? T : 1) * (size_t)(n > 0 ? n : 1));
+        double *D = (double *)calloc(4 * (size_t)(T > 0 ? T : 1) * (size_t)(n > 0 ? n : 1), sizeof(double));
+        for (int l = 0; l < n; l++) {
+            const int i = a0 + l;
+            double *S = SW + (size_t)l * 4 * (T + 1);
+            seg_choice *SC = SCW + (size_t)l * (T > 0 ? T : 1);
             S[0] = b->x[i]; S[1] = b->y[i]; S[2] = b->yaw[i]; S[3] = b->v[i];
             for (int t = 0; t < T; t++) {
                 double x = S[4 * t], y = S[4 * t + 1], th = S[4 * t + 2], v = S[4 * t + 3];
                 double a = actions[((int64_t)t * A + i) * 2], dl = actions[((int64_t)t * A + i) * 2 + 1];
-                move_one(c, &x, &y, &th, &v, L, a, dl);
+                move_one(c, &x, &y, &th, &v, b->len[i], a, dl);
                 S[4 * (t + 1)] = x; S[4 * (t + 1) + 1] = y; S[4 * (t + 1) + 2] = th; S[4 * (t + 1) + 3] = v;
                 SC[t] = nearest_edge(b, c, w, x, y);
                 if (SC[t].seg >= 0) SC[t].side = side_of(b, SC[t].seg, x, y);
             }
+        }
+        /* observation terms: D[(l * T + t) * 4 + k] = increment of dJ/ds_{t+1} of agent l */
+        if (grad_obs && P >= 0) {
+            for (int t = 0; t < T; t++) {
+                for (int l = 0; l < n; l++) {
+                    const int i = a0 + l;
+                    const double *Si = SW + (size_t)l * 4 * (T + 1) + 4 * (t + 1);
+                    const double x = Si[0], y = Si[1], th = Si[2];
+                    const double ct = cos(th), st = sin(th);
+                    const double *go = grad_obs + ((int64_t)t * A + i) * F;
+                    double *Di = D + ((size_t)l * T + t) * 4;
+                    /* speed, and the goal in the ego frame g' = R(-th)(g - p) */
+                    Di[3] += go[0];
+                    {
+                        const double dxg = b->gx[i] - x, dyg = b->gy[i] - y;
+                        const double gpx = ct * dxg + st * dyg, gpy = -st * dxg + ct * dyg;
+                        Di[0] += -ct * go[1] + st * go[2];
+                        Di[1] += -st * go[1] - ct * go[2];
+                        Di[2] += gpy * go[1] - gpx * go[2];
+                    }
+                    for (int sl = 0; sl < P; sl++) {
+                        const int j = sl < l ? sl : sl + 1;
+                        if (j >= n) continue;
+                        const double *Sj = SW + (size_t)j * 4 * (T + 1) + 4 * (t + 1);
+                        const double dx = Sj[0] - x, dy = Sj[1] - y;
+                        if (dx * dx + dy * dy > c->obs_radius * c->obs_radius) continue;
+                        const double fx = ct * dx + st * dy, fy = -st * dx + ct * dy;
+                        const double bx = go[3 + 4 * sl], by = go[4 + 4 * sl];
+                        const double bd = go[5 + 4 * sl], bv = go[6 + 4 * sl];
+                        double *Dj = D + ((size_t)j * T + t) * 4;
+                        /* f = R(-th_i)(p_j - p_i): dJ/dp_j = R(th_i) b = -dJ/dp_i */
+                        const double rx = ct * bx - st * by, ry = st * bx + ct * by;
+                        Dj[0] += rx;
+                        Dj[1] += ry;
+                        Di[0] -= rx;
+                        Di[1] -= ry;
+                        Di[2] += bx * fy - by * fx;
+                        /* heading difference th_j - th_i, partner speed v_j */
+                        Dj[2] += bd;
+                        Di[2] -= bd;
+                        Dj[3] += bv;
+                    }
+                }
+            }
+        }
+        for (int l = 0; l < n; l++) {
+            const int i = a0 + l;
+            double L = b->len[i];
+            const double *S = SW + (size_t)l * 4 * (T + 1);
+            const seg_choice *SC = SCW + (size_t)l * (T > 0 ? T : 1);
             /* reverse pass: lam = adjoint of s_{t+1} */
             double lx = 0.0, ly = 0.0, lth = 0.0, lv = 0.0;
             for (int t = T - 1; t >= 0; t--) {
+                const double *Dt = D + ((size_t)l * T + t) * 4;
+                lx += Dt[0];
+                ly += Dt[1];
+                lth += Dt[2];
+                lv += Dt[3];
                 double gr = grad_rewards[(int64_t)t * A + i];
                 /* reward r_t at s_{t+1}: goal term through the ego frame */
                 double x = S[4 * (t + 1)], y = S[4 * (t + 1) + 1], th = S[4 * (t + 1) + 2];
@@ -991,9 +1108,10 @@ void or_rollout_vjp(const or_batch *b, const or_config *c, int T, const double *
                 grad_state0[2 * (int64_t)A + i] = lth;
                 grad_state0[3 * (int64_t)A + i] = lv;
             }
-            free(S);
-            free(SC);
         }
+        free(SW);
+        free(SCW);
+        free(D);
     }
 }
 

@@ -91,7 +91,8 @@ def _declare(L):
     L.or_reset.argtypes = [vp, vp, vp, vp]
     L.or_step.argtypes = [vp, vp, vp, vp]
     L.or_rollout.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, d]
-    L.or_rollout_vjp.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+    L.or_rollout_vjp.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp]
+    L.or_rollout_obs.argtypes = [vp, vp, i32, vp, vp, vp]
 
 
 def _p(a):
@@ -292,7 +293,7 @@ class OracleSim:
         return coll, band
 
     # -- differentiable rollout --
-    def rollout(self, actions, tol=1e-6):
+    def rollout(self, actions, tol=1e-6, obs=False):
         T = actions.shape[0]
         act = np.ascontiguousarray(actions, dtype=np.float64)
         rew = np.zeros((T, self.A))
@@ -301,14 +302,38 @@ class OracleSim:
         un = np.zeros(self.A, np.uint8)
         lib().or_rollout(C.byref(self._batch()), C.byref(self.cfg), T, _p(act), _p(rew),
                          _p(states), _p(seg), _p(un), tol)
-        return dict(rewards=rew, states=states, seg=seg, unstable=un)
+        out = dict(rewards=rew, states=states, seg=seg, unstable=un)
+        if obs:
+            out["obs"], out["obs_band"] = self.rollout_obs(states)
+        return out
 
-    def rollout_vjp(self, actions, grad_rewards):
+    def obs_features(self) -> int:
+        """Features per agent-step of the rollout observation (speed, goal x', goal y',
+        then x', y', heading difference, speed of each of the P partner slots)."""
+        if self.params.partners < 0:
+            raise ValueError("the rollout observation needs a fixed number of partner slots")
+        return 3 + 4 * self.params.partners
+
+    def rollout_obs(self, states):
+        """Observation [T, A, F] of the states [T + 1, 4, A] after each step, and the band
+        [T, A] of its mask and wrap decisions."""
+        T = states.shape[0] - 1
+        st = np.ascontiguousarray(states, dtype=np.float64)
+        obs = np.zeros((T, self.A, self.obs_features()))
+        band = np.zeros((T, self.A), np.uint8)
+        lib().or_rollout_obs(C.byref(self._batch()), C.byref(self.cfg), T, _p(st), _p(obs), _p(band))
+        return obs, band
+
+    def rollout_vjp(self, actions, grad_rewards, grad_obs=None):
         T = actions.shape[0]
         act = np.ascontiguousarray(actions, dtype=np.float64)
         gr = np.ascontiguousarray(grad_rewards, dtype=np.float64)
+        go = None
+        if grad_obs is not None:
+            go = np.ascontiguousarray(grad_obs, dtype=np.float64)
+            assert go.shape == (T, self.A, self.obs_features())
         ga = np.zeros((T, self.A, 2))
         g0 = np.zeros((4, self.A))
         lib().or_rollout_vjp(C.byref(self._batch()), C.byref(self.cfg), T, _p(act), _p(gr),
-                             _p(ga), _p(g0))
+                             _p(go), _p(ga), _p(g0))
         return ga, g0

@@ -89,6 +89,15 @@ MUTANTS = [
     ("VJP simplified-model curvature", "grad_actions[((int64_t)t * A + i) * 2 + 1] = lth * d;",
      "grad_actions[((int64_t)t * A + i) * 2 + 1] = lth;"),
     ("VJP goal term sign", "lx += -ct * bgx + st * bgy;", "lx += ct * bgx + st * bgy;"),
+    # rollout observation and its VJP
+    ("rollout obs goal in the world frame", "                o[1] = ct * dxg + st * dyg;", "                o[1] = dxg;"),
+    ("rollout obs partner radius exclusive", "                    if (dx * dx + dy * dy > R * R) continue;",
+     "                    if (dx * dx + dy * dy >= R * R) continue;"),
+    ("rollout obs heading difference reversed", "const double dyaw = wrap_angle(S[2 * A + jj] - th);",
+     "const double dyaw = wrap_angle(th - S[2 * A + jj]);"),
+    ("obs VJP without the partner's position term", "                        Dj[0] += rx;\n                        Dj[1] += ry;\n", ""),
+    ("obs VJP rotation term sign", "Di[2] += bx * fy - by * fx;", "Di[2] -= bx * fy - by * fx;"),
+    ("obs VJP without the partner's speed", "                        Dj[3] += bv;\n", ""),
     # inversion and decimation
     ("inversion of a standing vehicle", "double st = fabs(d) < OR_INV_MIN_DIST ? 0.0 : w / d;", "double st = w / d;"),
     ("inversion without the heading wrap", "double w = wrap_angle(dth);", "double w = dth;"),
