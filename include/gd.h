@@ -255,20 +255,36 @@ gd_status gd_obs(gd_sim *sim, void *stream);
  * within the radius; ties -> lowest index).  This is a smooth instance of the
  * configurable agent-road distance rewards of Sec. 3.2 "Rewards".  Saves the state every
  * ckpt_every steps in ckpt [ceil(T/ckpt_every), 4, A] (x, y, yaw, speed) for
- * gd_rollout_bwd.  1 <= ckpt_every <= 32. */
+ * gd_rollout_bwd.  1 <= ckpt_every <= 32.
+ * states (nullable): [T, 4, A], the state after every step.  obs (nullable, needs states
+ * and a fixed number P of partner slots, else GD_E_UNSUPPORTED): [T, A, F] with
+ * F = 3 + 4P (gd_rollout_obs_features), the continuous part of the relative-frame
+ * observation (Fig. 1; Sec. 3.2 "Sensor modalities") of the state after each step: the
+ * agent's speed and its goal in its own frame (g'x, g'y), then for each partner slot s
+ * (the s-th other agent of its world in index order) the partner's position in the
+ * agent's frame, its heading minus the agent's, wrapped to [-pi, pi), and its speed when
+ * the partner lies within obs_radius (binary32 squared distance, inclusive), zeros
+ * otherwise.  The rollout removes no agent, so every agent is a visible partner. */
 gd_status gd_rollout_fwd(gd_sim *sim, const float *actions, int32_t T, int32_t ckpt_every,
-                         float *rewards, float *ckpt, void *stream);
+                         float *rewards, float *ckpt, float *states, float *obs, void *stream);
+
+/* Features per agent-step of the rollout observation, 3 + 4P (GD_E_UNSUPPORTED when the
+ * partner slots are ragged, partners = -1).  Host-side. */
+gd_status gd_rollout_obs_features(const gd_sim *sim, int32_t *features);
 
 /* Differentiable rollout (backward): vector-Jacobian product of gd_rollout_fwd.  Given
- * grad_rewards [T,A] = dJ/d rewards, writes grad_actions [T,A,2] = dJ/d actions and, if
- * non-NULL, grad_state0 [4,A] = dJ/d (x, y, yaw, speed) at t = 0.  Recomputes each
- * segment of ckpt_every steps from `ckpt` (the output of gd_rollout_fwd with the same
- * actions, T and ckpt_every).  The nearest-segment choice, the side and the clip activity
- * are held constant (they are piecewise constant); collision flags are not
- * differentiated. */
+ * grad_rewards [T,A] = dJ/d rewards and, if non-NULL, grad_obs [T,A,F] = dJ/d obs,
+ * writes grad_actions [T,A,2] = dJ/d actions and, if non-NULL, grad_state0 [4,A] =
+ * dJ/d (x, y, yaw, speed) at t = 0.  Recomputes each segment of ckpt_every steps from
+ * `ckpt` (the output of gd_rollout_fwd with the same actions, T and ckpt_every).  With
+ * grad_obs, `states` must be the state log of that forward (the observation couples the
+ * agents of a world: an agent's adjoint gathers the terms of every observation it
+ * appears in, read against the other agents' logged states).  The nearest-segment
+ * choice, the side, the clip activity, the partner masks and the heading wraps are held
+ * constant (they are piecewise constant); collision flags are not differentiated. */
 gd_status gd_rollout_bwd(gd_sim *sim, const float *actions, const float *ckpt, int32_t T,
-                         int32_t ckpt_every, const float *grad_rewards, float *grad_actions,
-                         float *grad_state0, void *stream);
+                         int32_t ckpt_every, const float *grad_rewards, const float *grad_obs,
+                         const float *states, float *grad_actions, float *grad_state0, void *stream);
 
 /* Expert-action inversion for the simplified model (Sec. 3.2 "Agent dynamics": the model is
  * invertible for unbounded actions, which makes logged trajectories usable as

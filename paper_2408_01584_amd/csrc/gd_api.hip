@@ -18,10 +18,12 @@
 namespace gdk {
 hipError_t launch_lidar_impl(const SimArgs &a, const LidarCtl &lc, hipStream_t s);
 hipError_t launch_rollout_fwd_impl(const SimArgs &a, const float2 *actions, int T, int C,
-                                   float *rewards, float *ckpt, hipStream_t s);
+                                   float *rewards, float *ckpt, float *states, hipStream_t s);
+hipError_t launch_rollout_obs_impl(const SimArgs &a, const float *states, int T, float *obs, hipStream_t s);
 hipError_t launch_rollout_bwd_impl(const SimArgs &a, const float2 *actions, const float *ckpt,
-                                   int T, int C, const float *grad_rewards, float2 *grad_actions,
-                                   float *grad_state0, hipStream_t s);
+                                   int T, int C, const float *grad_rewards, const float *grad_obs,
+                                   const float *states, float2 *grad_actions, float *grad_state0,
+                                   hipStream_t s);
 hipError_t launch_invert_actions_impl(const float *states, int T, int A, float dt, float *actions,
                                       hipStream_t s);
 constexpr int kMaxInvertSteps = 65535 * 16;  // launch chunks of 16 steps on grid axis y
@@ -603,32 +605,47 @@ gd_status gd_step(gd_sim *sim, const float *actions, void *stream) {
     return enqueue_step(sim, kModeStep, actions, nullptr, (hipStream_t)stream);
 }
 
+gd_status gd_rollout_obs_features(const gd_sim *sim, int32_t *features) {
+    if (!sim || !features) return fail(GD_E_ARG, "NULL argument");
+    if (sim->cfg.partners < 0)
+        return fail(GD_E_UNSUPPORTED, "the rollout observation needs a fixed number of partner slots");
+    *features = 3 + 4 * sim->cfg.partners;
+    return GD_OK;
+}
+
 gd_status gd_rollout_fwd(gd_sim *sim, const float *actions, int32_t T, int32_t ckpt_every,
-                         float *rewards, float *ckpt, void *stream) {
+                         float *rewards, float *ckpt, float *states, float *obs, void *stream) {
     if (!sim) return fail(GD_E_ARG, "sim is NULL");
     if (T < 0) return fail(GD_E_ARG, "T must be >= 0");
     if (ckpt_every < 1 || ckpt_every > 32) return fail(GD_E_ARG, "ckpt_every must be in [1, 32]");
+    if (obs && !states) return fail(GD_E_ARG, "the observation is formed from the state log: states is NULL");
+    if (obs && sim->cfg.partners < 0)
+        return fail(GD_E_UNSUPPORTED, "the rollout observation needs a fixed number of partner slots");
     if (T == 0 || sim->args.A == 0) return GD_OK;
     if (!actions || !rewards || !ckpt) return fail(GD_E_ARG, "NULL buffer");
     hipStream_t s = (hipStream_t)stream;
     TIMED(sim, s, GD_PHASE_ROLLOUT_FWD,
-          launch_rollout_fwd_impl(sim->args, (const float2 *)actions, T, ckpt_every, rewards, ckpt, s),
+          launch_rollout_fwd_impl(sim->args, (const float2 *)actions, T, ckpt_every, rewards, ckpt, states, s),
           "rollout forward launch");
+    if (obs) HIP_TRY(launch_rollout_obs_impl(sim->args, states, T, obs, s), "rollout observation launch");
     return GD_OK;
 }
 
 gd_status gd_rollout_bwd(gd_sim *sim, const float *actions, const float *ckpt, int32_t T,
-                         int32_t ckpt_every, const float *grad_rewards, float *grad_actions,
-                         float *grad_state0, void *stream) {
+                         int32_t ckpt_every, const float *grad_rewards, const float *grad_obs,
+                         const float *states, float *grad_actions, float *grad_state0, void *stream) {
     if (!sim) return fail(GD_E_ARG, "sim is NULL");
     if (T < 0) return fail(GD_E_ARG, "T must be >= 0");
     if (ckpt_every < 1 || ckpt_every > 32) return fail(GD_E_ARG, "ckpt_every must be in [1, 32]");
+    if (grad_obs && !states) return fail(GD_E_ARG, "grad_obs needs the forward's state log: states is NULL");
+    if (grad_obs && sim->cfg.partners < 0)
+        return fail(GD_E_UNSUPPORTED, "the rollout observation needs a fixed number of partner slots");
     if (T == 0 || sim->args.A == 0) return GD_OK;
     if (!actions || !ckpt || !grad_rewards || !grad_actions) return fail(GD_E_ARG, "NULL buffer");
     hipStream_t s = (hipStream_t)stream;
     TIMED(sim, s, GD_PHASE_ROLLOUT_BWD,
           launch_rollout_bwd_impl(sim->args, (const float2 *)actions, ckpt, T, ckpt_every, grad_rewards,
-                                  (float2 *)grad_actions, grad_state0, s),
+                                  grad_obs, grad_obs ? states : nullptr, (float2 *)grad_actions, grad_state0, s),
           "rollout backward launch");
     return GD_OK;
 }

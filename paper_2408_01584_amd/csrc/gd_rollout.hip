@@ -14,6 +14,13 @@
 // (x, y, yaw, v) is carried backwards through the reward and the dynamics, producing
 // dJ/d(accel, steer) for every step.  Segment choice, side and clip activity are held
 // constant; the result does not depend on ckpt_every.
+//
+// Observation (optional): the forward can log the state after every step, from which
+// k_rollout_obs forms the continuous observation of each agent (speed, goal in its frame;
+// per partner slot the partner's position in its frame, heading difference, speed --
+// Fig. 1, Sec. 3.2 "Sensor modalities").  Partners couple the agents of a world, so the
+// backward reads the other agents' states from that log: at each step an agent's adjoint
+// gathers the terms of its own observation and of every observation it appears in.
 #include "gd_internal.h"
 
 namespace gdk {
@@ -48,6 +55,15 @@ __device__ __forceinline__ void group_min(unsigned &hi, unsigned &lo, int &q) {
     GD_ROR_STEP(0xB1)   // quad_perm [1, 0, 3, 2]
     GD_ROR_STEP(0x4E)   // quad_perm [2, 3, 0, 1]
 #undef GD_ROR_STEP
+}
+
+// Sum over the 8 lanes of a group (every lane ends with the same total, summed in the same
+// order on every lane).
+__device__ __forceinline__ float group_sum(float v) {
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xf, 0xf, false));  // row_half_mirror
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xf, 0xf, false));   // quad_perm [1,0,3,2]
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xf, 0xf, false));   // quad_perm [2,3,0,1]
+    return v;
 }
 
 // nearest road-edge segment to (px, py) within R (ties -> lowest world-local index), by
@@ -167,7 +183,8 @@ __device__ __forceinline__ void world_of(const int *agent_off, int W, int i, int
 
 __global__ __launch_bounds__(kRollThreads) void k_rollout_fwd(SimArgs a, const float2 *__restrict__ act,
                                                               int T, int C, float *__restrict__ rewards,
-                                                              float *__restrict__ ckpt) {
+                                                              float *__restrict__ ckpt,
+                                                              float *__restrict__ slog) {
     // kGroup lanes per agent: the nearest-edge search is spread over them, the rest of
     // the step is computed by all of them alike and written by the first
     const int gid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -196,13 +213,72 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_fwd(SimArgs a, const f
         else bicycle_r(x, y, yaw, v, L, u.x, u.y, a.dt, a.vmax);
         const EdgeChoice ch = nearest_edge_group(g, ecs, es, eid, x, y, a.R_obs, sub);
         const float rw = smooth_reward(x, y, yaw, gx, gy, es, ch, a.R_obs);
-        if (sub == 0) rewards[(size_t)t * A + i] = rw;
+        if (sub == 0) {
+            rewards[(size_t)t * A + i] = rw;
+            if (slog) {
+                float *sl = slog + (size_t)t * 4 * A;
+                sl[i] = x;
+                sl[A + i] = y;
+                sl[2 * A + i] = yaw;
+                sl[3 * A + i] = v;
+            }
+        }
+    }
+}
+
+// Observation of the rollout from its state log slog [T, 4, A] (the state after each
+// step): obs [T, A, 3 + 4P] = (speed, goal x', goal y') then, per partner slot s (the
+// s-th other agent of the world in index order), (x', y', wrap(yaw_j - yaw), v_j) when
+// the partner lies within the radius (binary32 key, inclusive), zeros otherwise.  One wave
+// per (step, agent), a lane per feature.
+constexpr int kObsThreads = 256;
+__global__ __launch_bounds__(kObsThreads) void k_rollout_obs(SimArgs a, const float *__restrict__ slog,
+                                                             int T, float *__restrict__ obs) {
+    const long long item = (long long)blockIdx.x * (kObsThreads / kWave) + threadIdx.x / kWave;
+    const int lane = threadIdx.x & (kWave - 1);
+    const size_t A = (size_t)a.A;
+    if (item >= (long long)T * (long long)A) return;
+    const int t = (int)(item / (long long)A), i = (int)(item % (long long)A);
+    int w;
+    world_of(a.agent_off, a.W, i, w);
+    const int a0 = a.agent_off[w], n = a.agent_off[w + 1] - a0, l = i - a0;
+    const int P = a.P, F = 3 + 4 * P;
+    const float *S = slog + (size_t)t * 4 * A;
+    const float x = S[i], y = S[A + i], yaw = S[2 * A + i];
+    float sn, cs;
+    sincosf(yaw, &sn, &cs);
+    float *o = obs + ((size_t)t * A + i) * F;
+    for (int f = lane; f < F; f += kWave) {
+        float val = 0.0f;
+        if (f == 0) {
+            val = S[3 * A + i];
+        } else if (f < 3) {
+            const float dxg = a.gx[i] - x, dyg = a.gy[i] - y;
+            val = f == 1 ? cs * dxg + sn * dyg : -sn * dxg + cs * dyg;
+        } else {
+            const int sl = (f - 3) >> 2, k = (f - 3) & 3;
+            const int j = sl < l ? sl : sl + 1;
+            if (j < n) {
+                const int jj = a0 + j;
+                const float xj = S[jj], yj = S[A + jj];
+                if (key32(x, y, xj, yj) <= a.R2_obs) {
+                    const float dx = xj - x, dy = yj - y;
+                    val = k == 0 ? cs * dx + sn * dy
+                        : k == 1 ? -sn * dx + cs * dy
+                        : k == 2 ? wrap_pi(S[2 * A + jj] - yaw)
+                                 : S[3 * A + jj];
+                }
+            }
+        }
+        o[f] = val;
     }
 }
 
 __global__ __launch_bounds__(kRollThreads) void k_rollout_bwd(SimArgs a, const float2 *__restrict__ act,
                                                               const float *__restrict__ ckpt, int T, int C,
                                                               const float *__restrict__ grad_r,
+                                                              const float *__restrict__ grad_obs,
+                                                              const float *__restrict__ slog,
                                                               float2 *__restrict__ grad_a,
                                                               float *__restrict__ grad_s0) {
     // per thread: states before steps c0..c0+C (C+1 entries) and the segment choice of the
@@ -229,6 +305,8 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_bwd(SimArgs a, const f
     const float L = a.len[i], gxa = a.gx[i], gya = a.gy[i];
     const float dt = a.dt, vmax = a.vmax;
     const size_t A = (size_t)a.A;
+    const int a0 = a.agent_off[w], n = a.agent_off[w + 1] - a0, l = i - a0;
+    const int P = a.P, F = 3 + 4 * P;
     float lx = 0.f, ly = 0.f, lth = 0.f, lv = 0.f;  // adjoint of the state after the current step
     const int nseg = (T + C - 1) / C;
     for (int sgi = nseg - 1; sgi >= 0; sgi--) {
@@ -259,6 +337,59 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_bwd(SimArgs a, const f
             const float4 s1 = st[t - c0 + 1];
             float sn, cs;
             sincosf(s1.z, &sn, &cs);
+            if (grad_obs) {
+                // observation terms of step t, from the state log (the states the
+                // observation was formed from, so that the partner masks agree with it)
+                const float *S = slog + (size_t)t * 4 * A;
+                const float *go = grad_obs + ((size_t)t * A + i) * F;
+                const float xi = S[i], yi = S[A + i];
+                float oth, octh;
+                sincosf(S[2 * A + i], &oth, &octh);
+                float dx_ = 0.f, dy_ = 0.f, dth_ = 0.f, dv_ = 0.f;
+                if (sub == 0) {
+                    // own speed and goal in the own frame, g' = R(-yaw)(g - p)
+                    dv_ += go[0];
+                    const float dxg = gxa - xi, dyg = gya - yi;
+                    const float gpx = octh * dxg + oth * dyg, gpy = -oth * dxg + octh * dyg;
+                    dx_ += -octh * go[1] + oth * go[2];
+                    dy_ += -oth * go[1] - octh * go[2];
+                    dth_ += gpy * go[1] - gpx * go[2];
+                }
+                // own partner slots: f = R(-yaw_i)(p_j - p_i), wrap(yaw_j - yaw_i)
+                for (int sl = sub; sl < P; sl += kGroup) {
+                    const int j = sl < l ? sl : sl + 1;
+                    if (j >= n) continue;
+                    const int jj = a0 + j;
+                    const float xj = S[jj], yj = S[A + jj];
+                    if (!(key32(xi, yi, xj, yj) <= a.R2_obs)) continue;
+                    const float dx = xj - xi, dy = yj - yi;
+                    const float fx = octh * dx + oth * dy, fy = -oth * dx + octh * dy;
+                    const float bx = go[3 + 4 * sl], by = go[4 + 4 * sl], bd = go[5 + 4 * sl];
+                    dx_ -= octh * bx - oth * by;
+                    dy_ -= oth * bx + octh * by;
+                    dth_ += bx * fy - by * fx - bd;
+                }
+                // the slot of agent i in every other agent's observation
+                for (int m = sub; m < n; m += kGroup) {
+                    if (m == l) continue;
+                    const int sl = l < m ? l : l - 1;
+                    if (sl >= P) continue;
+                    const int mm = a0 + m;
+                    const float xm = S[mm], ym = S[A + mm];
+                    if (!(key32(xm, ym, xi, yi) <= a.R2_obs)) continue;
+                    float sm, cm;
+                    sincosf(S[2 * A + mm], &sm, &cm);
+                    const float *gm = grad_obs + ((size_t)t * A + mm) * F + 3 + 4 * sl;
+                    dx_ += cm * gm[0] - sm * gm[1];
+                    dy_ += sm * gm[0] + cm * gm[1];
+                    dth_ += gm[2];
+                    dv_ += gm[3];
+                }
+                lx += group_sum(dx_);
+                ly += group_sum(dy_);
+                lth += group_sum(dth_);
+                lv += group_sum(dv_);
+            }
             // goal term: r = -|g'|
             {
                 const float dxg = gxa - s1.x, dyg = gya - s1.y;
@@ -429,20 +560,30 @@ hipError_t launch_invert_actions_impl(const float *states, int T, int A, float d
 }
 
 hipError_t launch_rollout_fwd_impl(const SimArgs &a, const float2 *actions, int T, int C,
-                                   float *rewards, float *ckpt, hipStream_t s) {
+                                   float *rewards, float *ckpt, float *states, hipStream_t s) {
     if (C < 1 || C > kMaxCkpt) return hipErrorInvalidValue;
     const int blocks = (int)(((long long)a.A * kGroup + kRollThreads - 1) / kRollThreads);
-    hipLaunchKernelGGL(k_rollout_fwd, dim3(blocks), dim3(kRollThreads), 0, s, a, actions, T, C, rewards, ckpt);
+    hipLaunchKernelGGL(k_rollout_fwd, dim3(blocks), dim3(kRollThreads), 0, s, a, actions, T, C, rewards, ckpt,
+                       states);
+    return hipGetLastError();
+}
+
+hipError_t launch_rollout_obs_impl(const SimArgs &a, const float *states, int T, float *obs, hipStream_t s) {
+    const long long items = (long long)T * a.A;
+    const long long blocks = (items + kObsThreads / kWave - 1) / (kObsThreads / kWave);
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_rollout_obs, dim3((unsigned)blocks), dim3(kObsThreads), 0, s, a, states, T, obs);
     return hipGetLastError();
 }
 
 hipError_t launch_rollout_bwd_impl(const SimArgs &a, const float2 *actions, const float *ckpt, int T,
-                                   int C, const float *grad_rewards, float2 *grad_actions,
-                                   float *grad_state0, hipStream_t s) {
+                                   int C, const float *grad_rewards, const float *grad_obs,
+                                   const float *states, float2 *grad_actions, float *grad_state0,
+                                   hipStream_t s) {
     if (C < 1 || C > kMaxCkpt) return hipErrorInvalidValue;
     const int blocks = (int)(((long long)a.A * kGroup + kRollThreads - 1) / kRollThreads);
     hipLaunchKernelGGL(k_rollout_bwd, dim3(blocks), dim3(kRollThreads), 0, s, a, actions, ckpt, T, C,
-                       grad_rewards, grad_actions, grad_state0);
+                       grad_rewards, grad_obs, states, grad_actions, grad_state0);
     return hipGetLastError();
 }
 

@@ -22,7 +22,8 @@ GD_CLASS_VEHICLE, GD_CLASS_CYCLIST, GD_CLASS_PEDESTRIAN = 0, 1, 2
 GD_AUTO_RESET, GD_TERMINATE_ON_COLLISION, GD_CHECK_FINITE, GD_USE_GRAPH = 1, 2, 4, 8
 
 ENTRY_POINTS = ("gd_partner_slots", "gd_workspace_size", "gd_create", "gd_reset", "gd_step",
-                "gd_obs", "gd_rollout_fwd", "gd_rollout_bwd", "gd_invert_actions",
+                "gd_obs", "gd_rollout_fwd", "gd_rollout_obs_features", "gd_rollout_bwd",
+                "gd_invert_actions",
                 "gd_decimate_workspace_size", "gd_decimate", "gd_decimate_noalloc",
                 "gd_set_obs_buffers", "gd_set_timing",
                 "gd_get_timing", "gd_check", "gd_destroy", "gd_last_error")
@@ -80,8 +81,9 @@ def lib():
             "gd_reset": [vp, vp, vp],
             "gd_step": [vp, vp, vp],
             "gd_obs": [vp, vp],
-            "gd_rollout_fwd": [vp, vp, i32, i32, vp, vp, vp],
-            "gd_rollout_bwd": [vp, vp, vp, i32, i32, vp, vp, vp, vp],
+            "gd_rollout_fwd": [vp, vp, i32, i32, vp, vp, vp, vp, vp],
+            "gd_rollout_obs_features": [vp, C.POINTER(C.c_int32)],
+            "gd_rollout_bwd": [vp, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp],
             "gd_invert_actions": [vp, vp, i32, vp, vp],
             "gd_decimate_workspace_size": [i32, szp],
             "gd_decimate": [vp, i32, i32, vp, vp, C.c_float, vp, vp, vp, C.c_size_t, vp],
@@ -145,16 +147,25 @@ def gd_obs(sim, stream: int):
 
 
 def gd_rollout_fwd(sim, actions_ptr: int, T: int, ckpt_every: int, rewards_ptr: int,
-                   ckpt_ptr: int, stream: int):
+                   ckpt_ptr: int, states_ptr: int | None, obs_ptr: int | None, stream: int):
     _check(lib().gd_rollout_fwd(sim, C.c_void_p(actions_ptr), T, ckpt_every,
-                                C.c_void_p(rewards_ptr), C.c_void_p(ckpt_ptr), C.c_void_p(stream)))
+                                C.c_void_p(rewards_ptr), C.c_void_p(ckpt_ptr),
+                                C.c_void_p(states_ptr or 0), C.c_void_p(obs_ptr or 0),
+                                C.c_void_p(stream)))
+
+
+def gd_rollout_obs_features(sim) -> int:
+    out = C.c_int32(0)
+    _check(lib().gd_rollout_obs_features(sim, C.byref(out)))
+    return out.value
 
 
 def gd_rollout_bwd(sim, actions_ptr: int, ckpt_ptr: int, T: int, ckpt_every: int,
-                   grad_rewards_ptr: int, grad_actions_ptr: int, grad_state0_ptr: int | None,
-                   stream: int):
+                   grad_rewards_ptr: int, grad_obs_ptr: int | None, states_ptr: int | None,
+                   grad_actions_ptr: int, grad_state0_ptr: int | None, stream: int):
     _check(lib().gd_rollout_bwd(sim, C.c_void_p(actions_ptr), C.c_void_p(ckpt_ptr), T, ckpt_every,
-                                C.c_void_p(grad_rewards_ptr), C.c_void_p(grad_actions_ptr),
+                                C.c_void_p(grad_rewards_ptr), C.c_void_p(grad_obs_ptr or 0),
+                                C.c_void_p(states_ptr or 0), C.c_void_p(grad_actions_ptr),
                                 C.c_void_p(grad_state0_ptr or 0), C.c_void_p(stream)))
 
 

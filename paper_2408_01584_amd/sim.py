@@ -175,21 +175,37 @@ class Sim:
         return out
 
     # ---- differentiable rollout
-    def rollout_fwd(self, actions: torch.Tensor, ckpt_every: int = 10):
+    def rollout_fwd(self, actions: torch.Tensor, ckpt_every: int = 10, obs: bool = False):
+        """rewards [T, A] and checkpoints; with obs=True also the state log [T, 4, A] and
+        the observation [T, A, 3 + 4P] (returned as a third and fourth value)."""
         T = actions.shape[0]
         rewards = torch.empty((T, self.A), dtype=torch.float32, device=self.device)
         nck = max(1, math.ceil(T / ckpt_every))
         ckpt = torch.empty((nck, 4, self.A), dtype=torch.float32, device=self.device)
+        states = o = None
+        if obs:
+            F = G.gd_rollout_obs_features(self.handle)
+            states = torch.empty((T, 4, self.A), dtype=torch.float32, device=self.device)
+            o = torch.empty((T, self.A, F), dtype=torch.float32, device=self.device)
         G.gd_rollout_fwd(self.handle, actions.data_ptr(), T, ckpt_every, rewards.data_ptr(),
-                         ckpt.data_ptr(), _stream())
+                         ckpt.data_ptr(), None if states is None else states.data_ptr(),
+                         None if o is None else o.data_ptr(), _stream())
+        if obs:
+            return rewards, ckpt, states, o
         return rewards, ckpt
 
-    def rollout_bwd(self, actions, ckpt, grad_rewards, ckpt_every: int = 10, want_state0=False):
+    def rollout_bwd(self, actions, ckpt, grad_rewards, ckpt_every: int = 10, want_state0=False,
+                    grad_obs=None, states=None):
         T = actions.shape[0]
         ga = torch.empty((T, self.A, 2), dtype=torch.float32, device=self.device)
         g0 = torch.empty((4, self.A), dtype=torch.float32, device=self.device) if want_state0 else None
+        if grad_obs is not None:
+            assert states is not None and states.shape == (T, 4, self.A)
+            grad_obs = grad_obs.contiguous()
         G.gd_rollout_bwd(self.handle, actions.data_ptr(), ckpt.data_ptr(), T, ckpt_every,
-                         grad_rewards.contiguous().data_ptr(), ga.data_ptr(),
+                         grad_rewards.contiguous().data_ptr(),
+                         None if grad_obs is None else grad_obs.data_ptr(),
+                         None if grad_obs is None else states.data_ptr(), ga.data_ptr(),
                          None if g0 is None else g0.data_ptr(), _stream())
         return ga, g0
 
@@ -208,19 +224,32 @@ class Sim:
 class DiffRollout(torch.autograd.Function):
     """rewards [T, A] = rollout(actions [T, A, 2]) from the simulator's current state,
     differentiable with respect to the actions through the hand-written backward kernel
-    (checkpoints every ``ckpt_every`` steps, recomputed in the backward pass)."""
+    (checkpoints every ``ckpt_every`` steps, recomputed in the backward pass).  With
+    ``obs=True`` it returns (rewards, obs [T, A, 3 + 4P]), both differentiable."""
 
     @staticmethod
-    def forward(ctx, actions: torch.Tensor, sim: Sim, ckpt_every: int = 10):
+    def forward(ctx, actions: torch.Tensor, sim: Sim, ckpt_every: int = 10, obs: bool = False):
         actions = actions.detach().contiguous()
-        rewards, ckpt = sim.rollout_fwd(actions, ckpt_every)
         ctx.sim = sim
         ctx.ckpt_every = ckpt_every
+        ctx.obs = obs
+        if obs:
+            rewards, ckpt, states, o = sim.rollout_fwd(actions, ckpt_every, obs=True)
+            ctx.save_for_backward(actions, ckpt, states)
+            return rewards, o
+        rewards, ckpt = sim.rollout_fwd(actions, ckpt_every)
         ctx.save_for_backward(actions, ckpt)
         return rewards
 
     @staticmethod
-    def backward(ctx, grad_rewards):
-        actions, ckpt = ctx.saved_tensors
-        ga, _ = ctx.sim.rollout_bwd(actions, ckpt, grad_rewards.contiguous(), ctx.ckpt_every)
-        return ga, None, None
+    def backward(ctx, grad_rewards, grad_obs=None):
+        if ctx.obs:
+            actions, ckpt, states = ctx.saved_tensors
+            if grad_rewards is None:
+                grad_rewards = torch.zeros(actions.shape[:2], dtype=torch.float32, device=actions.device)
+            ga, _ = ctx.sim.rollout_bwd(actions, ckpt, grad_rewards.contiguous(), ctx.ckpt_every,
+                                        grad_obs=grad_obs, states=states if grad_obs is not None else None)
+        else:
+            actions, ckpt = ctx.saved_tensors
+            ga, _ = ctx.sim.rollout_bwd(actions, ckpt, grad_rewards.contiguous(), ctx.ckpt_every)
+        return ga, None, None, None

@@ -138,7 +138,9 @@ def test_null_handles(G):
     assert L.gd_obs(None, None) == G.GD_E_ARG
     assert L.gd_reset(None, None, None) == G.GD_E_ARG
     assert L.gd_check(None, None) == G.GD_E_ARG
-    assert L.gd_rollout_fwd(None, None, 1, 1, None, None, None) == G.GD_E_ARG
+    assert L.gd_rollout_fwd(None, None, 1, 1, None, None, None, None, None) == G.GD_E_ARG
+    assert L.gd_rollout_bwd(None, None, None, 1, 1, None, None, None, None, None, None) == G.GD_E_ARG
+    assert L.gd_rollout_obs_features(None, None) == G.GD_E_ARG
 
 
 def test_decimate_argument_checks(G):
