@@ -301,6 +301,7 @@ def main():
                      "bytes_per_agent_step": round(unit_bytes, 1), "avg_launch_ms": round(step_ms, 5),
                      "launches_timed": args.steps},
         "step": {"launch": "graph" if args.graph else "direct",
+                 "launch_shape": sim.launch or "library default",
                  "observed_agent_fraction": round(vis_frac, 4),
                  "active_agent_steps_per_s": round(value * vis_frac, 1)},
         # the paper's own figure, for context only: another simulator implementation, other

@@ -177,7 +177,8 @@ static long long partner_slots_of(const gd_config *c, const int32_t *h_agent_off
 // Launch shape of the step kernel: waves per workgroup, distance bins, candidate-list
 // entries per wave, and whether the road is staged in LDS.  Fields the config fixes are
 // kept; the rest maximise resident waves per compute unit (counting only the workgroups
-// the batch can fill), then the number of resident workgroups, then a candidate list of
+// the batch can fill, as far as LDS and the kernel's registers allow), then the number of
+// resident workgroups, then a candidate list of
 // at least 512 entries (the smallest such), then 512 bins, then staged edge segments.
 // GD_ROAD_AUTO stages the road when that keeps as many resident waves as reading it
 // through the caches (the road then costs no memory round trips in the observation
@@ -209,7 +210,9 @@ static Shape best_shape(const gd_config *c, bool staged, int max_road, int cell_
                     const size_t lds = step_lds_bytes(wv, nb, K, K ? cc : 0, rc, cell_cap4, ec,
                                                       agent_cap, idx16);
                     if (lds > (size_t)kLdsBytes) continue;
-                    const int wgs = std::min({(int)((size_t)kLdsBytes / lds), 32 / wv, wgs_needed});
+                    const int wgs = std::min({(int)((size_t)kLdsBytes / lds),
+                                              step_waves_per_cu(nb, staged, idx16) / wv, wgs_needed});
+                    if (wgs < 1) continue;
                     // resident waves first; at equal waves, more workgroups of at least 8
                     // waves, whose world phases then overlap other workgroups' observation
                     // phases (smaller workgroups serialise too many agents per wave)

@@ -120,6 +120,7 @@ hipError_t launch_build_grid(const SimArgs &a, float cell_size, hipStream_t s);
 hipError_t launch_step(const SimArgs &a, const StepCtl &c, int waves, int bins, hipStream_t s);
 size_t step_lds_bytes(int waves, int NB, int K, int ccap, int road_cap, int cell_cap4,
                       int edge_cap, int agent_cap, bool idx16);
+int step_waves_per_cu(int bins, bool staged, bool idx16);
 
 // ---------------------------------------------------------------- device helpers
 

@@ -33,6 +33,8 @@
 //      once (no slot table).
 // A cut bin too large for the staging array is resolved element by element by a wave
 // min-reduction (exact, slow, for pathological point clusters only).
+#include <algorithm>
+
 #include "gd_internal.h"
 
 namespace gdk {
@@ -924,6 +926,44 @@ static bool node_one(const SimArgs *a, const StepCtl *c, int waves, hipKernelNod
     p.kernelParams = args;
     p.extra = nullptr;
     return true;
+}
+
+// Waves per compute unit that the registers of this instantiation allow (4 SIMDs, at
+// most 8 waves each, 512 VGPRs per lane per SIMD in granules of 8); 20 when the runtime
+// does not report the count.
+template <int NB, int RM>
+static int vgpr_waves_per_cu() {
+    static int cached = 0;
+    if (!cached) {
+        hipFuncAttributes at{};
+        int w = 20;
+        if (hipFuncGetAttributes(&at, (const void *)k_step<NB, RM>) == hipSuccess && at.numRegs > 0) {
+            const int regs = (at.numRegs + 7) / 8 * 8;
+            w = 4 * std::min(8, 512 / regs);
+        }
+        cached = w;
+    }
+    return cached;
+}
+
+template <int NB>
+static int waves_nb(int rm) {
+    switch (rm) {
+        case kRoadLds: return vgpr_waves_per_cu<NB, kRoadLds>();
+        case kRoadGlobal16: return vgpr_waves_per_cu<NB, kRoadGlobal16>();
+        default: return vgpr_waves_per_cu<NB, kRoadGlobal32>();
+    }
+}
+
+int step_waves_per_cu(int bins, bool staged, bool idx16) {
+    const int rm = staged ? kRoadLds : (idx16 ? kRoadGlobal16 : kRoadGlobal32);
+    switch (bins) {
+        case 64: return waves_nb<64>(rm);
+        case 128: return waves_nb<128>(rm);
+        case 512: return waves_nb<512>(rm);
+        case 1024: return waves_nb<1024>(rm);
+        default: return waves_nb<256>(rm);
+    }
 }
 
 static int road_mode(const StepCtl &c) {

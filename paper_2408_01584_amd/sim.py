@@ -55,8 +55,19 @@ class Sim:
     Buffers are exposed as torch tensors in ``self.buf``; ``gd_step`` and friends update
     them in place on the current stream."""
 
-    def __init__(self, scene, params=None, device="cuda", **launch):
+    def __init__(self, scene, params=None, device="cuda", tuned=True, **launch):
+        """``launch``: explicit launch-shape fields (cell_size, obs_waves, obs_bins,
+        obs_cands, obs_road) and graph; without shape fields and with ``tuned``, the shape
+        the autotuner cached for this workload on this device is used when there is one
+        (every shape gives the same results)."""
         self.params = params if params is not None else scene.params
+        shape_keys = ("cell_size", "obs_waves", "obs_bins", "obs_cands", "obs_road")
+        if tuned and not any(k in launch for k in shape_keys):
+            from .tune import cached_shape
+            cs = cached_shape(scene, self.params, bool(launch.get("graph", False)))
+            if cs:
+                launch = {**launch, **cs}
+        self.launch = {k: v for k, v in launch.items() if k in shape_keys}
         self.device = torch.device(device)
         self.h_agent_off = np.ascontiguousarray(scene.agent_off, dtype=np.int32)
         self.h_road_off = np.ascontiguousarray(scene.road_off, dtype=np.int32)

@@ -23,9 +23,10 @@ CACHE = os.environ.get("GD_TUNE_CACHE", os.path.join(os.path.dirname(os.path.abs
 DEFAULT_SPACE = [
     dict(obs_waves=w, obs_bins=b, obs_cands=c, cell_size=cs, obs_road=rd)
     for rd in (1, 2)  # GD_ROAD_LDS, GD_ROAD_GLOBAL
-    for (w, c) in ((16, 512), (16, 768), (12, 768), (8, 768))
+    for w in (16, 12, 8)
+    for c in (512, 768)
     for b in (256, 512, 1024)
-    for cs in (10.0, 12.0, 15.0)
+    for cs in (10.0, 15.0)
 ]
 
 
@@ -74,6 +75,13 @@ def time_shape(scene, params, shape, actions, steps=20, warmup=5, graph=False) -
         sim.close()
 
 
+def cached_shape(scene, params=None, graph=False):
+    """The launch shape the autotuner found for this workload on this device, or None."""
+    params = params if params is not None else scene.params
+    rec = _load().get(signature(scene, params, graph) + "@" + _device_name())
+    return None if rec is None else dict(rec["shape"])
+
+
 def autotune(scene, params=None, space=None, steps=20, warmup=5, graph=False, use_cache=True,
              verbose=False) -> dict:
     """Fastest launch shape for this scene on this device (cached)."""
@@ -109,3 +117,24 @@ def autotune(scene, params=None, space=None, steps=20, warmup=5, graph=False, us
             json.dump(cache, f, indent=1, sort_keys=True)
         os.replace(tmp, CACHE)
     return dict(best)
+
+
+def main():
+    """python -m paper_2408_01584_amd.tune --config N [...]: tune the workload's launch
+    shape on this device and cache it (GD_TUNE_CACHE names the cache file)."""
+    import argparse
+
+    from .scenes import make_scene
+    ap = argparse.ArgumentParser(description=main.__doc__.split(":")[0])
+    ap.add_argument("--config", type=int, nargs="+", default=[1])
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--graph", action="store_true")
+    args = ap.parse_args()
+    for c in args.config:
+        scene = make_scene(c)
+        best = autotune(scene, steps=args.steps, graph=args.graph, verbose=True)
+        print(json.dumps({"config": c, "shape": best}), flush=True)
+
+
+if __name__ == "__main__":
+    main()
