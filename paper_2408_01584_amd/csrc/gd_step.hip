@@ -384,17 +384,22 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
                 for (int j = lane; j < n; j += kWave) {
                     const int fj = sf[j];
                     const float xj = sx[j], yj = sy[j], cj = sc[j], sj = ss[j], Lj = sL[j], Wj = sW[j];
-                    const float dj = sqrtf(Lj * Lj + Wj * Wj);
+                    // bounding circles (the hardware square root's 1-ulp error is far inside the
+                    // 1 mm margin)
+                    const float dj = __builtin_amdgcn_sqrtf(Lj * Lj + Wj * Wj);
 #pragma unroll
                     for (int k = 0; k < PI; k++) {
                         // a pair needs an alive agent; a parked agent is an obstacle only
                         const bool alive_i = (fi[k] & GD_FLAG_ALIVE) != 0;
-                        if (j <= i0 + k * nwaves || !(fi[k] & (GD_FLAG_ALIVE | GD_FLAG_STATIC))) continue;
-                        if (!(fj & (alive_i ? (GD_FLAG_ALIVE | GD_FLAG_STATIC) : GD_FLAG_ALIVE))) continue;
                         const float dx = xj - xi[k], dy = yj - yi[k];
-                        const float rr = 0.5f * (sqrtf(Li[k] * Li[k] + Wi[k] * Wi[k]) + dj) + 1e-3f;
-                        if (dx * dx + dy * dy > rr * rr) continue;
-                        if (sat_box_box(dx, dy, ci[k], si[k], Li[k], Wi[k], cj, sj, Lj, Wj) < 0.0f) {
+                        const float rr = 0.5f * (__builtin_amdgcn_sqrtf(Li[k] * Li[k] + Wi[k] * Wi[k]) + dj) + 1e-3f;
+                        const bool cand = j > i0 + k * nwaves && (fi[k] & (GD_FLAG_ALIVE | GD_FLAG_STATIC)) &&
+                                          (fj & (alive_i ? (GD_FLAG_ALIVE | GD_FLAG_STATIC) : GD_FLAG_ALIVE)) &&
+                                          dx * dx + dy * dy <= rr * rr;
+                        // few pairs pass the circles: the separating-axis test runs only when
+                        // a lane has one (a wave-uniform branch, not a predicated block)
+                        if (__ballot(cand) == 0ull) continue;
+                        if (cand && sat_box_box(dx, dy, ci[k], si[k], Li[k], Wi[k], cj, sj, Lj, Wj) < 0.0f) {
                             hit[k] = true;
                             if (fj & GD_FLAG_ALIVE) atomicOr(&scoll[j], (int)GD_FLAG_COLL_AGENT);
                         }
@@ -435,10 +440,12 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
                     for (int q = e0 + sub; q < e1; q += tpa) {
                         const float4 e = es[q];
                         const float x0 = e.x - xi, y0 = e.y - yi, x1 = e.z - xi, y1 = e.w - yi;
-                        if (fminf(x0, x1) > ex || fmaxf(x0, x1) < -ex || fminf(y0, y1) > ey ||
-                            fmaxf(y0, y1) < -ey)
-                            continue;
-                        if (sat_box_seg(ci, si, hL, hW, x0, y0, x1, y1) < 0.0f) hit = true;
+                        const bool cand = !(fminf(x0, x1) > ex || fmaxf(x0, x1) < -ex || fminf(y0, y1) > ey ||
+                                            fmaxf(y0, y1) < -ey);
+                        // few segments pass the box's extent: separating axes only when a lane
+                        // has one
+                        if (__ballot(cand) == 0ull) continue;
+                        if (cand && sat_box_seg(ci, si, hL, hW, x0, y0, x1, y1) < 0.0f) hit = true;
                     }
                 }
                 if (hit) atomicOr(&scoll[i], (int)GD_FLAG_COLL_EDGE);
