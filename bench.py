@@ -300,6 +300,8 @@ def main():
                      "traffic": traffic, "algorithmic_bytes_per_launch": int(launch_bytes),
                      "bytes_per_agent_step": round(unit_bytes, 1), "avg_launch_ms": round(step_ms, 5),
                      "launches_timed": args.steps},
+        # the same kernel against the vector-ALU ceiling (its instruction counters)
+        "roofline_alu": alu_roofline("k_step", WORKLOAD_TAG, step_ms),
         "step": {"launch": "graph" if args.graph else "direct",
                  "launch_shape": sim.launch or "library default",
                  "observed_agent_fraction": round(vis_frac, 4),
