@@ -599,24 +599,22 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
         if (S > 0) {
             const long long base = a.P >= 0 ? (long long)ai * a.P : pbase_w + (long long)l * S;
             for (int s = lane; s < S; s += kWave) {
+                // every slot computed and then masked (no nested branches): padding slots
+                // (j >= n) read the observer's own entry
                 const int j = s < l ? s : s + 1;
-                float f0 = 0.f, f1 = 0.f, f2 = 0.f, f3 = 0.f, f4 = 0.f, f5 = 0.f;
-                uint8_t m = 0;
-                if (vis && j < n && (sf[j] & GD_FLAG_VISIBLE) && key32(px, py, sx[j], sy[j]) <= R2) {
-                    const float dx = sx[j] - px, dy = sy[j] - py;
-                    f0 = csy * dx + sny * dy;
-                    f1 = -sny * dx + csy * dy;
-                    f2 = wrap_pi(syaw[j] - yaw);
-                    f3 = sv[j];
-                    f4 = sL[j];
-                    f5 = sW[j];
-                    m = 1;
-                }
+                const int jj = j < n ? j : l;
+                const float xj = sx[jj], yj = sy[jj], yawj = syaw[jj];
+                const float vj = sv[jj], Lj = sL[jj], Wj = sW[jj];
+                const bool m = vis && j < n && (sf[jj] & GD_FLAG_VISIBLE) && key32(px, py, xj, yj) <= R2;
+                const float dx = xj - px, dy = yj - py;
+                const float f0 = csy * dx + sny * dy;
+                const float f1 = -sny * dx + csy * dy;
+                const float f2 = wrap_pi(yawj - yaw);
                 float2 *po = reinterpret_cast<float2 *>(a.partner + (size_t)(base + s) * 6);
-                po[0] = make_float2(f0, f1);
-                po[1] = make_float2(f2, f3);
-                po[2] = make_float2(f4, f5);
-                a.pmask[base + s] = m;
+                po[0] = m ? make_float2(f0, f1) : make_float2(0.f, 0.f);
+                po[1] = m ? make_float2(f2, vj) : make_float2(0.f, 0.f);
+                po[2] = m ? make_float2(Lj, Wj) : make_float2(0.f, 0.f);
+                a.pmask[base + s] = m ? 1 : 0;
             }
         }
         if (K == 0) continue;
