@@ -180,6 +180,13 @@ __host__ __device__ inline size_t wave_lds_bytes(int NB, int K, int ccap, bool i
 
 constexpr int kAgentArrays = 13;  // x y yaw v L W cos sin goal_x goal_y flags coll bound
 
+// one field of the agents' records in LDS (record of kAgentArrays words per agent)
+template <typename T>
+struct AgentField {
+    T *base;
+    __device__ __forceinline__ T &operator[](int i) const { return base[i * kAgentArrays]; }
+};
+
 // Road modes of the step kernel: where phase 5 reads the road, and the index width.
 enum RoadMode { kRoadGlobal32 = 0, kRoadGlobal16 = 1, kRoadLds = 2 };
 
@@ -219,12 +226,15 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
     int *scells = reinterpret_cast<int *>(saux + (STAGED ? c.road_cap : 0));
     float *sag = reinterpret_cast<float *>(scells + (STAGED ? c.cell_cap4 : 0));
     const int ac = c.agent_cap;
-    float *sx = sag, *sy = sag + ac, *syaw = sag + 2 * ac, *sv = sag + 3 * ac;
-    float *sL = sag + 4 * ac, *sW = sag + 5 * ac, *sc = sag + 6 * ac, *ss = sag + 7 * ac;
-    float *sgx = sag + 8 * ac, *sgy = sag + 9 * ac;
-    int *sf = reinterpret_cast<int *>(sag + 10 * ac);
-    int *scoll = reinterpret_cast<int *>(sag + 11 * ac);
-    float *sbound = sag + 12 * ac;  // bound on the distance of the agent's K-th road point
+    // one record of kAgentArrays words per agent (an odd stride: lanes reading one field
+    // of consecutive agents hit distinct banks), so that all fields of an agent share one
+    // address and differ by immediate offsets
+    const AgentField<float> sx{sag}, sy{sag + 1}, syaw{sag + 2}, sv{sag + 3};
+    const AgentField<float> sL{sag + 4}, sW{sag + 5}, sc{sag + 6}, ss{sag + 7};
+    const AgentField<float> sgx{sag + 8}, sgy{sag + 9};
+    const AgentField<int> sf{reinterpret_cast<int *>(sag + 10)};
+    const AgentField<int> scoll{reinterpret_cast<int *>(sag + 11)};
+    const AgentField<float> sbound{sag + 12};  // bound on the distance of the agent's K-th road point
     unsigned char *uni = reinterpret_cast<unsigned char *>(sag + kAgentArrays * ac);
     float4 *sedge = reinterpret_cast<float4 *>(uni);
     int *secells = reinterpret_cast<int *>(sedge + c.edge_cap);
