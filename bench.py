@@ -438,7 +438,8 @@ def secondary(args):
         sim = Sim(scene, graph=graph)
         run_steps(sim, 10)()
         ms = _timed(run_steps(sim, T))
-        out[name] = {"ms_per_step": round(ms / T, 5), "value": round(A * T / (ms / 1e3), 1)}
+        out[name] = {"ms_per_step": round(ms / T, 5), "value": round(A * T / (ms / 1e3), 1),
+                     "launch_shape": sim.launch or "library default"}
         if name == "direct":
             out["value"] = out[name]["value"]
             out["ms_per_step"] = out[name]["ms_per_step"]

@@ -41,9 +41,11 @@ def signature(scene, params, graph: bool) -> str:
 
 
 def _device_name() -> str:
+    """Device key: architecture and compute-unit count (the marketing name is left out: it
+    depends on whether the driver's ID table is installed, and a profiler can change it)."""
     import torch
     p = torch.cuda.get_device_properties(0)
-    return "%s:%s:%d" % (p.name, getattr(p, "gcnArchName", ""), p.multi_processor_count)
+    return "%s:%d" % (getattr(p, "gcnArchName", ""), p.multi_processor_count)
 
 
 def _load():
@@ -78,7 +80,12 @@ def time_shape(scene, params, shape, actions, steps=20, warmup=5, graph=False) -
 def cached_shape(scene, params=None, graph=False):
     """The launch shape the autotuner found for this workload on this device, or None."""
     params = params if params is not None else scene.params
-    rec = _load().get(signature(scene, params, graph) + "@" + _device_name())
+    cache, dev = _load(), "@" + _device_name()
+    rec = cache.get(signature(scene, params, graph) + dev)
+    if rec is None and graph:
+        # a launch shape is a property of the kernel, not of how it is launched: without a
+        # record of its own, a graph-mode simulator takes the direct-launch shape
+        rec = cache.get(signature(scene, params, False) + dev)
     return None if rec is None else dict(rec["shape"])
 
 
