@@ -163,7 +163,8 @@ typedef struct {
                                   length, width; S from gd_partner_slots */
     uint8_t *partner_mask;     /* [S] 1 = slot holds an observed partner */
     float *obs_road;           /* [A,K,4] x', y', direction wrap(dir - yaw), type */
-    int32_t *road_idx;         /* [A,K] world-local index of the road point, -1 = empty */
+    int32_t *road_idx;         /* [A,K] world-local index of the road point, -1 = empty;
+                                  NULL = not written (4 B per slot less) */
     float *lidar;              /* [A,N] hit distance (m); NULL when N = 0 */
     int32_t *lidar_hit;        /* [A,N] 0 none, 1 road edge, 2 agent; NULL when N = 0 */
     float *reward;             /* [A] reward of the last step */

@@ -385,8 +385,8 @@ gd_status gd_create(const gd_config *cfg, const int32_t *h_agent_off, const int3
         return fail(GD_E_ARG, "road buffers are NULL");
     const long long S = partner_slots_of(cfg, h_agent_off);
     if (S > 0 && (!b->obs_partner || !b->partner_mask)) return fail(GD_E_ARG, "partner buffers are NULL");
-    if (cfg->top_k > 0 && A > 0 && (!b->obs_road || !b->road_idx))
-        return fail(GD_E_ARG, "road obs buffers are NULL");
+    if (cfg->top_k > 0 && A > 0 && !b->obs_road)
+        return fail(GD_E_ARG, "obs_road is NULL");
     if (cfg->lidar_rays > 0 && A > 0 && (!b->lidar || !b->lidar_hit))
         return fail(GD_E_ARG, "lidar buffers are NULL");
     if (((uintptr_t)b->workspace) & 255) return fail(GD_E_ARG, "workspace must be 256-byte aligned");
@@ -761,8 +761,8 @@ gd_status gd_set_obs_buffers(gd_sim *sim, const gd_buffers *b) {
     if (!b->obs_ego) return fail(GD_E_ARG, "buffer obs_ego is NULL");
     if (sim->slots > 0 && (!b->obs_partner || !b->partner_mask))
         return fail(GD_E_ARG, "partner buffers are NULL");
-    if (a.K > 0 && a.A > 0 && (!b->obs_road || !b->road_idx))
-        return fail(GD_E_ARG, "road obs buffers are NULL");
+    if (a.K > 0 && a.A > 0 && !b->obs_road)
+        return fail(GD_E_ARG, "obs_road is NULL");
     if (a.N > 0 && a.A > 0 && (!b->lidar || !b->lidar_hit)) return fail(GD_E_ARG, "lidar buffers are NULL");
     a.ego = b->obs_ego;
     a.partner = b->obs_partner;

@@ -630,11 +630,12 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
         if (K == 0) continue;
 
         float4 *out = reinterpret_cast<float4 *>(a.road + (size_t)ai * K * 4);
-        int *oidx = a.road_idx + (size_t)ai * K;
+        // the indices are optional: a null buffer is not written
+        int *oidx = a.road_idx ? a.road_idx + (size_t)ai * K : nullptr;
         if (!vis) {
             for (int s = lane; s < K; s += kWave) {
                 out[s] = make_float4(0.f, 0.f, 0.f, 0.f);
-                oidx[s] = -1;
+                if (oidx) oidx[s] = -1;
             }
             if (lane == 0) a.kth[ai] = R2;
             continue;
@@ -842,14 +843,14 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
                 dd = dd >= 3.14159265358979323846f ? dd - 6.283185307179586f : dd;
                 dd = dd < -3.14159265358979323846f ? dd + 6.283185307179586f : dd;
                 out[fin] = make_float4(csy * dx + sny * dy, -sny * dx + csy * dy, dd, (float)((unsigned)bits >> 24));
-                oidx[fin] = bits & 0xffffff;
+                if (oidx) oidx[fin] = bits & 0xffffff;
             }
             kk = fin == K - 1 ? k : kk;
         }
         // slots beyond the points in the radius
         for (int s = nsel + lane; s < K; s += kWave) {
             out[s] = make_float4(0.f, 0.f, 0.f, 0.f);
-            oidx[s] = -1;
+            if (oidx) oidx[s] = -1;
         }
         // the K-th key (R^2 when fewer than K points are in the radius), kept for the next
         // step's pruned radius
@@ -882,7 +883,7 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
                     out[s] = make_float4(csy * dx + sny * dy, -sny * dx + csy * dy,
                                          wrap_pi(a.rdir[r0 + idx] - yaw),
                                          (float)(a.rmeta[r0 + idx] & 0xff));
-                    oidx[s] = idx;
+                    if (oidx) oidx[s] = idx;
                 }
             }
         }

@@ -55,11 +55,12 @@ class Sim:
     Buffers are exposed as torch tensors in ``self.buf``; ``gd_step`` and friends update
     them in place on the current stream."""
 
-    def __init__(self, scene, params=None, device="cuda", tuned=True, **launch):
+    def __init__(self, scene, params=None, device="cuda", tuned=True, emit_road_idx=True, **launch):
         """``launch``: explicit launch-shape fields (cell_size, obs_waves, obs_bins,
         obs_cands, obs_road) and graph; without shape fields and with ``tuned``, the shape
         the autotuner cached for this workload on this device is used when there is one
-        (every shape gives the same results)."""
+        (every shape gives the same results).  ``emit_road_idx=False`` leaves the road
+        point indices unwritten (no ``road_idx`` buffer)."""
         self.params = params if params is not None else scene.params
         shape_keys = ("cell_size", "obs_waves", "obs_bins", "obs_cands", "obs_road")
         if tuned and not any(k in launch for k in shape_keys):
@@ -94,7 +95,7 @@ class Sim:
         b["obs_partner"] = torch.zeros((max(S, 1), 6), dtype=torch.float32, device=dev)
         b["partner_mask"] = torch.zeros(max(S, 1), dtype=torch.uint8, device=dev)
         b["obs_road"] = torch.zeros((A, max(K, 1), 4), dtype=torch.float32, device=dev)
-        b["road_idx"] = torch.zeros((A, max(K, 1)), dtype=torch.int32, device=dev)
+        b["road_idx"] = torch.zeros((A, max(K, 1)), dtype=torch.int32, device=dev) if emit_road_idx else None
         b["lidar"] = torch.zeros((A, max(N, 1)), dtype=torch.float32, device=dev)
         b["lidar_hit"] = torch.zeros((A, max(N, 1)), dtype=torch.int32, device=dev)
         b["reward"] = torch.zeros(A, dtype=torch.float32, device=dev)
@@ -141,7 +142,7 @@ class Sim:
         """Write the next observations into these tensors (e.g. a slot of a rollout ring)."""
         b = G.gd_buffers()
         b.obs_ego, b.obs_partner, b.partner_mask = ego.data_ptr(), partner.data_ptr(), pmask.data_ptr()
-        b.obs_road, b.road_idx = road.data_ptr(), road_idx.data_ptr()
+        b.obs_road, b.road_idx = road.data_ptr(), None if road_idx is None else road_idx.data_ptr()
         if lidar is not None:
             b.lidar, b.lidar_hit = lidar.data_ptr(), lidar_hit.data_ptr()
         G.gd_set_obs_buffers(self.handle, b)
@@ -175,13 +176,14 @@ class Sim:
         b = self.buf
         K, N, S = self.params.top_k, self.params.lidar_rays, self.S
         return dict(ego=b["obs_ego"], partner=b["obs_partner"][:S], pmask=b["partner_mask"][:S],
-                    road=b["obs_road"][:, :K], road_idx=b["road_idx"][:, :K],
+                    road=b["obs_road"][:, :K],
+                    road_idx=None if b["road_idx"] is None else b["road_idx"][:, :K],
                     lidar=b["lidar"][:, :N], lidar_hit=b["lidar_hit"][:, :N], reward=b["reward"],
                     flags=b["flags"], world_done=b["world_done"], t=b["t"])
 
     def host_outputs(self) -> dict:
         torch.cuda.current_stream().synchronize()
-        out = {k: v.cpu().numpy() for k, v in self.outputs().items()}
+        out = {k: v.cpu().numpy() for k, v in self.outputs().items() if v is not None}
         out["state"] = self.state().cpu().numpy()
         return out
 

@@ -123,6 +123,36 @@ def test_graph_mode_bitwise_equal(gpu):
             assert np.array_equal(a[n], b[n]), (k, n)
 
 
+def test_road_idx_optional(gpu):
+    """Without a road_idx buffer the step writes no indices and every other output keeps
+    the same bits (road staged in LDS and read through the caches; direct and graph
+    launches; the top-K's slow paths through a 4-entry candidate list)."""
+    from paper_2408_01584_amd import scenes as S
+    import torch
+    cases = [(1, [0, 1], {}), (2, [3, 4, 5], {"obs_road": 2}), (1, [2], {"obs_cands": 128, "obs_road": 2}),
+             (0, None, {"graph": True})]
+    for cfg, worlds, kw in cases:
+        sc = S.make_scene(cfg, worlds=worlds) if worlds else S.make_scene(cfg)
+        acts = torch.as_tensor(S.make_actions(cfg, 6, sc.num_agents), device="cuda")
+        ref = _sim(sc, **kw)
+        lean = _sim(sc, emit_road_idx=False, **kw)
+        assert lean.outputs()["road_idx"] is None
+        for k in range(6):
+            ref.step(acts[k])
+            lean.step(acts[k])
+            a, b = ref.host_outputs(), lean.host_outputs()
+            assert "road_idx" not in b
+            for n in b:
+                assert np.array_equal(a[n], b[n], equal_nan=True), (cfg, kw, k, n)
+        ref.obs()
+        lean.obs()
+        a, b = ref.host_outputs(), lean.host_outputs()
+        for n in b:
+            assert np.array_equal(a[n], b[n], equal_nan=True), (cfg, kw, "obs", n)
+        ref.close()
+        lean.close()
+
+
 def test_autotuner_picks_a_listed_shape_with_the_same_bits(gpu, tmp_path, monkeypatch):
     """tune.autotune times the given launch shapes on the device and returns the fastest;
     the simulator at that shape gives the same bits as the library default."""
