@@ -466,6 +466,23 @@ def secondary(args):
         del sim
         torch.cuda.empty_cache()
 
+    if c in (0, 2):
+        # the caller captures a whole episode's direct-launch steps in one HIP graph
+        sim = Sim(scene)
+        run_steps(sim, 10)()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            run_steps(sim, T)()
+        torch.cuda.synchronize()
+        ms = _timed(g.replay)
+        out["captured"] = {"ms_per_step": round(ms / T, 5), "value": round(A * T / (ms / 1e3), 1),
+                           "note": "%d steps captured by the caller in one HIP graph (torch.cuda.graph)" % T}
+        del g
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+
     if c in (3, 4):
         C = 10
         sim = Sim(scene)

@@ -153,6 +153,41 @@ def test_road_idx_optional(gpu):
         lean.close()
 
 
+def test_caller_captured_steps(gpu):
+    """gd_step in direct mode only launches kernels, so a caller can capture a loop of steps
+    in one HIP graph (here through torch.cuda.graph); every replay, with eager work and
+    synchronisations between replays, gives the bits of the same steps launched directly."""
+    from paper_2408_01584_amd import scenes as S
+    import torch
+    for cfg, worlds in ((0, None), (2, [3, 4, 5, 6])):
+        sc = S.make_scene(cfg, worlds=worlds) if worlds else S.make_scene(cfg)
+        n = 5
+        acts = torch.as_tensor(S.make_actions(cfg, n, sc.num_agents), device="cuda")
+        cap, ref = _sim(sc), _sim(sc)
+        for k in range(2):  # warm-up outside the capture (first launches set kernel attributes)
+            cap.step(acts[k])
+            ref.step(acts[k])
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for k in range(n):
+                cap.step(acts[k])
+        torch.cuda.synchronize()
+        for rep in range(3):
+            g.replay()
+            torch.cuda.synchronize()
+            for k in range(n):
+                ref.step(acts[k])
+            a, b = ref.host_outputs(), cap.host_outputs()
+            for name in a:
+                assert np.array_equal(a[name], b[name], equal_nan=True), (cfg, rep, name)
+            # eager work between replays
+            _ = (cap.buf["x"] * 2).sum().item()
+        del g
+        cap.close()
+        ref.close()
+
+
 def test_autotuner_picks_a_listed_shape_with_the_same_bits(gpu, tmp_path, monkeypatch):
     """tune.autotune times the given launch shapes on the device and returns the fastest;
     the simulator at that shape gives the same bits as the library default."""
