@@ -822,9 +822,17 @@ __global__ __launch_bounds__(1024) void k_step(SimArgs a, StepCtl c) {
             const int lo = b > 0 ? hist[b - 1] : 0;
             const int hi = hist[b];
             // mates with a smaller key, and with a smaller or equal one (itself included):
-            // a difference above 1 means an exact key tie
-            int rank = 0, rank_le = 0;
-            for (int m = lo; m < hi; m++) {
+            // a difference above 1 means an exact key tie.  A bin holds one to a few points:
+            // the first four are read together (one LDS round trip, indices clamped to the
+            // bin, which holds at least this point), the rest one by one
+            const int nm = hi - lo;
+            const float *mk = skey + lo;
+            const float ka = mk[0], kb = mk[min(1, nm - 1)], kc = mk[min(2, nm - 1)], kd = mk[min(3, nm - 1)];
+            int rank = (int)(ka < k) + ((nm > 1) & (int)(kb < k)) + ((nm > 2) & (int)(kc < k)) +
+                       ((nm > 3) & (int)(kd < k));
+            int rank_le = (int)(ka <= k) + ((nm > 1) & (int)(kb <= k)) + ((nm > 2) & (int)(kc <= k)) +
+                          ((nm > 3) & (int)(kd <= k));
+            for (int m = lo + 4; m < hi; m++) {
                 const float ko = skey[m];
                 rank += (int)(ko < k);
                 rank_le += (int)(ko <= k);
