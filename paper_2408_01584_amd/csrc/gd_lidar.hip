@@ -93,8 +93,11 @@ __device__ __forceinline__ void lidar_candidate(float ax, float ay, float bx, fl
         if (CONE) {
             k = m < n01 ? k0 + m : k2 + (m - n01);  // in [0, N) already
         } else {
-            k = (k0 + m) % N;
-            if (k < 0) k += N;
+            // k0 >= -N/2 - 1 and k0 + m <= N + 1 (arcs are at most a turn), so one
+            // correction each way replaces the modulo (an integer division on the GPU)
+            k = k0 + m;
+            k = k < 0 ? k + N : k;
+            k = k >= N ? k - N : k;
         }
         const float2 d = dirs[k];
         // ray t*d against a + s*e: t = nt / den, s = ns / den; the range tests are taken
