@@ -107,7 +107,9 @@ __device__ EdgeChoice nearest_edge_group(const WorldGrid &g, const int *ecs, con
                     const float ex = e.z - e.x, ey = e.w - e.y;
                     const float ax = e.x - px, ay = e.y - py;
                     const float ee = ex * ex + ey * ey;
-                    float u = ee > 0.0f ? -(ax * ex + ay * ey) / ee : 0.0f;
+                    // closest point with the hardware reciprocal (1 ulp; ties closer than
+                    // the 1e-4 m band are decided alike by the forward and its recompute)
+                    float u = ee > 0.0f ? -(ax * ex + ay * ey) * __builtin_amdgcn_rcpf(ee) : 0.0f;
                     u = fminf(fmaxf(u, 0.0f), 1.0f);
                     const float qx = ax + u * ex, qy = ay + u * ey;
                     const float d = sqrtf(qx * qx + qy * qy);
@@ -163,7 +165,8 @@ __device__ __forceinline__ float smooth_reward(float x, float y, float yaw, floa
         const float bpx = ct * bx + st * by, bpy = -st * bx + ct * by;
         const float ex = bpx - apx, ey = bpy - apy;
         const float ee = ex * ex + ey * ey;
-        float u = ee > 0.0f ? -(apx * ex + apy * ey) / ee : 0.0f;
+        // (the backward forms u with the same expression, so their clamp decisions agree)
+        float u = ee > 0.0f ? -(apx * ex + apy * ey) * __builtin_amdgcn_rcpf(ee) : 0.0f;
         u = fminf(fmaxf(u, 0.0f), 1.0f);
         const float qx = apx + u * ex, qy = apy + u * ey;
         s = ch.side * sqrtf(qx * qx + qy * qy);
@@ -303,6 +306,7 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_bwd(SimArgs a, const f
     const float4 *es = a.eseg + r0;
     const int *eid = a.eseg_id + r0;
     const float L = a.len[i], gxa = a.gx[i], gya = a.gy[i];
+    const float iL = 1.0f / L;  // once per agent: the adjoint's divisions by L become products
     const float dt = a.dt, vmax = a.vmax;
     const size_t A = (size_t)a.A;
     const int a0 = a.agent_off[w], n = a.agent_off[w + 1] - a0, l = i - a0;
@@ -396,7 +400,8 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_bwd(SimArgs a, const f
                 const float gpx = cs * dxg + sn * dyg, gpy = -sn * dxg + cs * dyg;
                 const float ng = sqrtf(gpx * gpx + gpy * gpy);
                 if (ng > 0.0f) {
-                    const float bgx = -gpx / ng * gr, bgy = -gpy / ng * gr;
+                    const float ing = __builtin_amdgcn_rcpf(ng);
+                    const float bgx = -gpx * ing * gr, bgy = -gpy * ing * gr;
                     lx += -cs * bgx + sn * bgy;
                     ly += -sn * bgx - cs * bgy;
                     lth += gpy * bgx - gpx * bgy;
@@ -412,7 +417,8 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_bwd(SimArgs a, const f
                 const float bpx = cs * bx + sn * by, bpy = -sn * bx + cs * by;
                 const float ex = bpx - apx, ey = bpy - apy;
                 const float ee = ex * ex + ey * ey;
-                float u = ee > 0.0f ? -(apx * ex + apy * ey) / ee : 0.0f;
+                const float iee = __builtin_amdgcn_rcpf(ee);
+                float u = ee > 0.0f ? -(apx * ex + apy * ey) * iee : 0.0f;
                 const bool cl = u <= 0.0f || u >= 1.0f;
                 u = fminf(fmaxf(u, 0.0f), 1.0f);
                 const float qx = apx + u * ex, qy = apy + u * ey;
@@ -422,16 +428,17 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_bwd(SimArgs a, const f
                 const float dbar = side * sbar;
                 float bqx = 0.f, bqy = 0.f;
                 if (d > 0.0f) {
-                    bqx = dbar * qx / d;
-                    bqy = dbar * qy / d;
+                    const float id = __builtin_amdgcn_rcpf(d);
+                    bqx = dbar * qx * id;
+                    bqy = dbar * qy * id;
                 }
                 float bapx = bqx, bapy = bqy, bex = u * bqx, bey = u * bqy;
                 if (!cl && ee > 0.0f) {
                     const float ubar = bqx * ex + bqy * ey;
-                    bapx += ubar * (-ex / ee);
-                    bapy += ubar * (-ey / ee);
-                    bex += ubar * (-apx / ee - 2.0f * u * ex / ee);
-                    bey += ubar * (-apy / ee - 2.0f * u * ey / ee);
+                    bapx += ubar * (-ex * iee);
+                    bapy += ubar * (-ey * iee);
+                    bex += ubar * (-apx * iee - 2.0f * u * ex * iee);
+                    bey += ubar * (-apy * iee - 2.0f * u * ey * iee);
                 }
                 const float bbpx = bex, bbpy = bey;
                 bapx -= bex;
@@ -464,14 +471,14 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_bwd(SimArgs a, const f
             const float tdl = tanf(u.y), beta = atanf(0.5f * tdl);
             const float cb = cosf(beta), sbt = sinf(beta);
             const float sec2 = 1.0f + tdl * tdl;
-            const float dbeta = 0.5f * sec2 / (1.0f + 0.25f * tdl * tdl);
+            const float dbeta = 0.5f * sec2 * __builtin_amdgcn_rcpf(1.0f + 0.25f * tdl * tdl);
             float sp, cp;
             sincosf(s0.z + beta, &sp, &cp);
-            const float bvb = lx * cp * dt + ly * sp * dt + lth * cb * tdl / L * dt;
+            const float bvb = lx * cp * dt + ly * sp * dt + lth * cb * tdl * iL * dt;
             const float bphi = -lx * vb * sp * dt + ly * vb * cp * dt;
             const float bth = lth + bphi;
-            const float bbeta = bphi - lth * vb * sbt * tdl / L * dt;
-            const float bdl = lth * vb * cb * sec2 / L * dt + bbeta * dbeta;
+            const float bbeta = bphi - lth * vb * sbt * tdl * iL * dt;
+            const float bdl = lth * vb * cb * sec2 * iL * dt + bbeta * dbeta;
             const float bv = bvb * c1f + lv * c2f;
             const float ba = bvb * c1f * 0.5f * dt + lv * c2f * dt;
             if (sub == 0) grad_a[(size_t)t * A + i] = make_float2(ba, bdl);
