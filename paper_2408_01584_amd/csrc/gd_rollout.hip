@@ -133,7 +133,8 @@ __device__ EdgeChoice nearest_edge_group(const WorldGrid &g, const int *ecs, con
 }
 
 __device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.0f) + log1pf(expf(-fabsf(z))); }
-__device__ __forceinline__ float sigmoidf(float z) { return 1.0f / (1.0f + expf(-z)); }
+// (the hardware reciprocal: 1 ulp, far inside the gradient tolerance)
+__device__ __forceinline__ float sigmoidf(float z) { return __builtin_amdgcn_rcpf(1.0f + expf(-z)); }
 
 __device__ __forceinline__ void bicycle_r(float &x, float &y, float &yaw, float &v, float L,
                                           float acc, float steer, float dt, float vmax) {
