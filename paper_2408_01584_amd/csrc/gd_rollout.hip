@@ -136,14 +136,27 @@ __device__ __forceinline__ float softplusf(float z) { return fmaxf(z, 0.0f) + lo
 // (the hardware reciprocal: 1 ulp, far inside the gradient tolerance)
 __device__ __forceinline__ float sigmoidf(float z) { return __builtin_amdgcn_rcpf(1.0f + expf(-z)); }
 
+// slip angle beta = atan(tan(steer) / 2) through its cosine and sine, cos beta =
+// 1 / sqrt(1 + z^2), sin beta = z cos beta (z = tan(steer) / 2), and the direction of
+// motion by angle addition: one tangent and one sincos per step instead of an arctangent,
+// a cosine and a sincos (the forward and the backward's recompute share this function)
+__device__ __forceinline__ void slip(float steer, float yaw, float &ts, float &cb, float &sb,
+                                     float &sp, float &cp) {
+    ts = tanf(steer);
+    const float z = 0.5f * ts;
+    cb = __builtin_amdgcn_rsqf(1.0f + z * z);
+    sb = z * cb;
+    float sy, cy;
+    sincosf(yaw, &sy, &cy);
+    sp = sy * cb + cy * sb;
+    cp = cy * cb - sy * sb;
+}
+
 __device__ __forceinline__ void bicycle_r(float &x, float &y, float &yaw, float &v, float L,
                                           float acc, float steer, float dt, float vmax) {
     float vb = fminf(fmaxf(v + 0.5f * acc * dt, -vmax), vmax);
-    float ts = tanf(steer);
-    float beta = atanf(0.5f * ts);
-    float sp, cp;
-    sincosf(yaw + beta, &sp, &cp);
-    float cb = cosf(beta);
+    float ts, cb, sb, sp, cp;
+    slip(steer, yaw, ts, cb, sb, sp, cp);
     x = x + vb * cp * dt;
     y = y + vb * sp * dt;
     yaw = yaw + vb * cb * ts / L * dt;
@@ -469,12 +482,10 @@ __global__ __launch_bounds__(kRollThreads) void k_rollout_bwd(SimArgs a, const f
             const float c1f = (vb_raw > -vmax && vb_raw < vmax) ? 1.0f : 0.0f;
             const float vn_raw = s0.w + u.x * dt;
             const float c2f = (vn_raw > -vmax && vn_raw < vmax) ? 1.0f : 0.0f;
-            const float tdl = tanf(u.y), beta = atanf(0.5f * tdl);
-            const float cb = cosf(beta), sbt = sinf(beta);
+            float tdl, cb, sbt, sp, cp;
+            slip(u.y, s0.z, tdl, cb, sbt, sp, cp);
             const float sec2 = 1.0f + tdl * tdl;
             const float dbeta = 0.5f * sec2 * __builtin_amdgcn_rcpf(1.0f + 0.25f * tdl * tdl);
-            float sp, cp;
-            sincosf(s0.z + beta, &sp, &cp);
             const float bvb = lx * cp * dt + ly * sp * dt + lth * cb * tdl * iL * dt;
             const float bphi = -lx * vb * sp * dt + ly * vb * cp * dt;
             const float bth = lth + bphi;
