@@ -81,11 +81,13 @@ __device__ EdgeChoice nearest_edge_group(const WorldGrid &g, const int *ecs, con
     const int cx = (int)fminf(fmaxf(fx, -1.0e6f), 1.0e6f);
     const int cy = (int)fminf(fmaxf(fy, -1.0e6f), 1.0e6f);
     const int rmax = (int)ceilf((R + g.max_seg) * g.inv_cs) + 1;
+    // segments are ranked by their binary32 squared distance (the square root, monotone,
+    // is taken once per ring and for the winner only)
     unsigned bhi = 0x7f800000u, blo = 0xffffffffu;  // (+inf, no index)
     int bq = -1;
     for (int r = 0; r <= rmax; r++) {
         group_min(bhi, blo, bq);
-        const float best = __uint_as_float(bhi);
+        const float best = sqrtf(__uint_as_float(bhi));
         if (best <= R && best + g.max_seg + 1e-3f * g.cs < (float)(r - 1) * g.cs) break;
         const int y0 = max(cy - r, 0), y1 = min(cy + r, g.ny - 1);
         for (int yy = y0; yy <= y1; yy++) {
@@ -112,8 +114,8 @@ __device__ EdgeChoice nearest_edge_group(const WorldGrid &g, const int *ecs, con
                     float u = ee > 0.0f ? -(ax * ex + ay * ey) * __builtin_amdgcn_rcpf(ee) : 0.0f;
                     u = fminf(fmaxf(u, 0.0f), 1.0f);
                     const float qx = ax + u * ex, qy = ay + u * ey;
-                    const float d = sqrtf(qx * qx + qy * qy);
-                    const unsigned dh = __float_as_uint(d), k = (unsigned)eid[q];
+                    const float d2 = qx * qx + qy * qy;
+                    const unsigned dh = __float_as_uint(d2), k = (unsigned)eid[q];
                     if (dh < bhi || (dh == bhi && k < blo)) {
                         bhi = dh;
                         blo = k;
@@ -124,7 +126,7 @@ __device__ EdgeChoice nearest_edge_group(const WorldGrid &g, const int *ecs, con
         }
     }
     group_min(bhi, blo, bq);
-    if (!(__uint_as_float(bhi) <= R) || bq < 0) return ch;
+    if (!(sqrtf(__uint_as_float(bhi)) <= R) || bq < 0) return ch;
     ch.q = bq;
     const float4 e = es[bq];
     const float cr = (e.z - e.x) * (py - e.y) - (e.w - e.y) * (px - e.x);
